@@ -1,0 +1,615 @@
+/*
+ * arc_oracle.c -- plain FP64 CPU oracle for the adaptive HEALPix ray-tracing
+ * radiative-transfer step of Hartley & Ricotti (arXiv:1807.07094).
+ *
+ * TEST INFRASTRUCTURE ONLY: it is the yardstick the GPU library is checked
+ * against, and it is deliberately slow and literal. Only the test-suite, the smoke
+ * check and the benchmark's CPU-baseline leg may load it.
+ *
+ * What it follows
+ *   - Section 2.1 (program design), steps (iii a-d): per source, root rays at radius 0
+ *     and zero optical depth; each ray is traced until it splits, terminates or leaves
+ *     the volume; a split makes four children at the next HEALPix level that start at
+ *     the parent's radius and keep the parent's optical depth.
+ *   - Section 2.2: polychromatic packets, one optical depth per frequency bin summed
+ *     over all absorbing species.
+ *   - Section 2.4 and eq:ion: cell-by-cell stepping to the next x, y or z boundary; the
+ *     photons a ray loses in a cell, S (1 - exp(-dtau)), are deposited there and
+ *     removed from the ray, so photons are conserved.
+ *   - Section 2.7 (eq:diffeq, eq:anninos, sub-cycle step) and section 2.8 for the
+ *     chemistry and energy update.
+ *
+ * Readings of points the paper leaves open (each is also listed in the design notes):
+ *   - Split radius: a level-l ray subtends 4 pi/(12 4^l) sr and splits once its
+ *     cross-section exceeds one cell face over Phi (Phi = rays per cell area, fig. 1 and
+ *     the methodology test), i.e. at r = 2^l sqrt(3/(pi Phi)) cells. The base value is
+ *     rounded once to float; levels beyond the one whose split radius exceeds the box
+ *     diagonal do not split.
+ *   - Directions are the HEALPix pixel centres rounded to float (not renormalised); the
+ *     ray is x(t) = xs + t d with t taken as the path length in cells.
+ *   - Children start at xs + t_split * d_child, not at the parent's end point.
+ *   - Per-ray rate: S_b / (12 4^l) exp(-tau_b) (section 2.4, equal solid angles).
+ *   - Termination: after a crossing in which every bin has tau_b >= -ln(eps_term) and
+ *     every bin's dtau_b >= 0.01, the remaining photons are absorbed in that cell, so
+ *     emitted = absorbed + escaped stays exact. Photons that leave the box are lost.
+ *   - Species split inside a bin in proportion to each species' optical depth.
+ *   - Tie rules: along an axis with d > 0 a point on a boundary belongs to the upper
+ *     cell, with d < 0 to the lower cell, with d = 0 to the upper cell; boundaries
+ *     reached at exactly the same t are crossed together.
+ *   - Every geometric decision is made exactly: positions lie on a 2^-12 lattice and
+ *     directions and split radii are floats, so every product compared below has at
+ *     most 48 significant bits and is exact in double.
+ */
+#include "arc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_MAXB 8
+#define ORC_DTAU_TERM_MIN 0.01
+
+static const double KB_ERG = 1.380649e-16;     /* Boltzmann constant [erg/K] */
+static const double EV_ERG = 1.602176634e-12;  /* electron volt [erg] */
+
+/* ------------------------------------------------------------------------------ */
+/* HEALPix, nested scheme (Gorski et al. 2005).                                     */
+/* ------------------------------------------------------------------------------ */
+
+int64_t orc_npix(int32_t level) { return (int64_t)12 << (2 * level); }
+
+/* Split a nested index into its base face and the (x, y) position inside the face;
+ * inside a face the nested index interleaves the bits of x (even) and y (odd). */
+static void nest_face_xy(int32_t level, int64_t pix, int* face, int64_t* ix, int64_t* iy)
+{
+    const int64_t per_face = (int64_t)1 << (2 * level);
+    *face = (int)(pix / per_face);
+    const int64_t in_face = pix % per_face;
+    int64_t x = 0, y = 0;
+    for (int bit = 0; bit < level; ++bit) {
+        x |= ((in_face >> (2 * bit)) & 1) << bit;
+        y |= ((in_face >> (2 * bit + 1)) & 1) << bit;
+    }
+    *ix = x;
+    *iy = y;
+}
+
+void orc_healpix_vec(int32_t level, int64_t pix, double v[3])
+{
+    /* Layout of the 12 base faces: the ring (in units of Nside) holding each face's
+     * southern corner, and the longitude index of that corner in units of pi/4. */
+    static const int face_ring[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
+    static const int face_lon[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
+    int face;
+    int64_t ix, iy;
+    nest_face_xy(level, pix, &face, &ix, &iy);
+    const int64_t ns = (int64_t)1 << level;
+
+    /* Ring index counted from the north pole, 1 .. 4 Nside - 1. */
+    const int64_t ring = face_ring[face] * ns - ix - iy - 1;
+    int64_t nr;      /* pixels per ring quadrant */
+    int shift;       /* 1 when the ring's pixel centres are offset by half a pixel */
+    double z;
+    if (ring < ns) {                 /* north polar cap: z = 1 - i^2 / (3 Nside^2) */
+        nr = ring;
+        shift = 0;
+        z = (double)(3 * ns * ns - nr * nr) / (double)(3 * ns * ns);
+    } else if (ring > 3 * ns) {      /* south polar cap, mirror image */
+        nr = 4 * ns - ring;
+        shift = 0;
+        z = -(double)(3 * ns * ns - nr * nr) / (double)(3 * ns * ns);
+    } else {                         /* equatorial belt: z = 4/3 - 2 i / (3 Nside) */
+        nr = ns;
+        shift = (int)((ring - ns) & 1);
+        z = (double)(2 * (2 * ns - ring)) / (double)(3 * ns);
+    }
+    /* Pixel number inside the ring, 1 .. 4 nr. */
+    int64_t j = (face_lon[face] * nr + ix - iy + 1 + shift) / 2;
+    if (j > 4 * nr) j -= 4 * nr;
+    if (j < 1) j += 4 * nr;
+
+    /* phi = (pi/2) (2j - 1 - shift) / (2 nr); reduce to a quadrant exactly so that
+     * centres on the axes come out with exact zero components. */
+    const int64_t num = 2 * j - 1 - shift, den = 2 * nr;
+    const int64_t quad = num / den, rem = num - quad * den;
+    const double a = (ORC_PI / 2) * ((double)rem / (double)den);
+    const double ca = cos(a), sa = sin(a);
+    double cx, cy;
+    switch (quad) {
+        case 0: cx = ca; cy = sa; break;
+        case 1: cx = -sa; cy = ca; break;
+        case 2: cx = -ca; cy = -sa; break;
+        default: cx = sa; cy = -ca; break;
+    }
+    const double st = sqrt((1.0 - z) * (1.0 + z));
+    v[0] = st * cx;
+    v[1] = st * cy;
+    v[2] = z;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Split radius.                                                                    */
+/* ------------------------------------------------------------------------------ */
+
+double orc_t_split(double rays_per_cell, int32_t level)
+{
+    /* pi r^2 / (3 4^l) = 1 / Phi  =>  r = 2^l sqrt(3 / (pi Phi)) */
+    const float base = (float)sqrt(3.0 / (ORC_PI * rays_per_cell));
+    return ldexp((double)base, level);
+}
+
+int32_t orc_auto_max_level(int32_t nx, int32_t ny, int32_t nz, double rays_per_cell)
+{
+    const double diag = sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
+    int32_t l = 0;
+    while (orc_t_split(rays_per_cell, l) < diag) ++l;
+    return l;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Cell-by-cell walk with exact decisions.                                          */
+/* ------------------------------------------------------------------------------ */
+
+typedef struct {
+    double xs[3];     /* ray origin (source position) */
+    double d[3];      /* direction, float-valued */
+    int64_t c[3];     /* current cell */
+    double t;         /* current path length */
+    double t_end;     /* split radius, or INFINITY */
+} walk_t;
+
+/* Index of the cell the ray occupies just after path length t0 along one axis.
+ * x = xs + t0 d. p = t0 d is exact in double; k - xs is exact (lattice), so each
+ * comparison below is exact. */
+static int64_t start_index(double xs, double t0, double d)
+{
+    if (d == 0.0) return (int64_t)floor(xs);
+    const double p = t0 * d;
+    int64_t k = (int64_t)floor(xs + p);   /* first guess, corrected exactly below */
+    if (d > 0) {                          /* largest k with xs + p >= k */
+        while (p < (double)k - xs) --k;
+        while (p >= (double)(k + 1) - xs) ++k;
+    } else {                              /* k with k < xs + p <= k + 1 */
+        while (p <= (double)k - xs) --k;
+        while (p > (double)(k + 1) - xs) ++k;
+    }
+    return k;
+}
+
+static int walk_inside(const walk_t* w, int32_t nx, int32_t ny, int32_t nz)
+{
+    return w->c[0] >= 0 && w->c[0] < nx && w->c[1] >= 0 && w->c[1] < ny && w->c[2] >= 0 &&
+           w->c[2] < nz;
+}
+
+/* Returns 1 if the start cell is inside the grid. */
+static int walk_start(walk_t* w, const double xs[3], const double d[3], double t0, double t_end,
+                      int32_t nx, int32_t ny, int32_t nz)
+{
+    for (int i = 0; i < 3; ++i) {
+        w->xs[i] = xs[i];
+        w->d[i] = d[i];
+        w->c[i] = start_index(xs[i], t0, d[i]);
+    }
+    w->t = t0;
+    w->t_end = t_end;
+    return walk_inside(w, nx, ny, nz);
+}
+
+/* Path length at which the current segment ends. *at_end = 1 if it ends at the split
+ * radius (which wins an exact tie with a boundary); *mask = axes whose boundary is
+ * reached exactly at that length. */
+static double walk_next(const walk_t* w, int* at_end, int* mask)
+{
+    /* t_i = a_i / e_i with a_i = distance of the next boundary from the origin along
+     * the axis and e_i = |d_i|; compare t_i < t_j as a_i e_j < a_j e_i. */
+    double a[3], e[3];
+    int best = -1;
+    for (int i = 0; i < 3; ++i) {
+        if (w->d[i] > 0) {
+            a[i] = (double)(w->c[i] + 1) - w->xs[i];
+            e[i] = w->d[i];
+        } else if (w->d[i] < 0) {
+            a[i] = w->xs[i] - (double)w->c[i];
+            e[i] = -w->d[i];
+        } else {
+            a[i] = 1.0;
+            e[i] = 0.0;
+            continue;
+        }
+        if (best < 0 || a[i] * e[best] < a[best] * e[i]) best = i;
+    }
+    *mask = 0;
+    for (int i = 0; i < 3; ++i)
+        if (e[i] > 0 && a[i] * e[best] == a[best] * e[i]) *mask |= 1 << i;
+    if (w->t_end < INFINITY && w->t_end * e[best] <= a[best]) {
+        *at_end = 1;
+        return w->t_end;
+    }
+    *at_end = 0;
+    return a[best] / e[best];
+}
+
+static void walk_advance(walk_t* w, int mask, double t_next)
+{
+    for (int i = 0; i < 3; ++i)
+        if (mask & (1 << i)) w->c[i] += (w->d[i] > 0) ? 1 : -1;
+    w->t = t_next;
+}
+
+int64_t orc_walk(int32_t nx, int32_t ny, int32_t nz, const double xs[3], const double d[3],
+                 double t0, double t_end, int64_t* cells, double* ds, int64_t cap, int32_t* how)
+{
+    walk_t w;
+    if (!walk_start(&w, xs, d, t0, t_end < 0 ? INFINITY : t_end, nx, ny, nz)) {
+        *how = 2;
+        return 0;
+    }
+    int64_t n = 0;
+    for (;;) {
+        int at_end, mask;
+        const double tn = walk_next(&w, &at_end, &mask);
+        if (n < cap) {
+            cells[n] = w.c[0] + (int64_t)nx * (w.c[1] + (int64_t)ny * w.c[2]);
+            ds[n] = tn - w.t;
+        }
+        ++n;
+        if (at_end) {
+            *how = 1;
+            return n;
+        }
+        walk_advance(&w, mask, tn);
+        if (!walk_inside(&w, nx, ny, nz)) {
+            *how = 0;
+            return n;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Tracer.                                                                          */
+/* ------------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t level;
+    int64_t pix;
+    double tau[ORC_MAXB];
+} ray_t;
+
+typedef struct {
+    ray_t* v;
+    int64_t n, cap;
+} stack_t_;
+
+static int push(stack_t_* s, const ray_t* r)
+{
+    if (s->n == s->cap) {
+        const int64_t nc = s->cap ? 2 * s->cap : 1024;
+        ray_t* nv = (ray_t*)realloc(s->v, (size_t)nc * sizeof(ray_t));
+        if (!nv) return -1;
+        s->v = nv;
+        s->cap = nc;
+    }
+    s->v[s->n++] = *r;
+    return 0;
+}
+
+/* g(x) = (1 - e^-x) / x, the mean attenuation over a segment of optical depth x. */
+static double mean_atten(double x) { return x > 0 ? -expm1(-x) / x : 1.0; }
+
+int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, const orc_params* p,
+                  double* J, double* gdir, uint64_t* tree, int64_t tree_cap, orc_ledger* led)
+{
+    if (!g || !s || !b || !p || !J || !led) return -1;
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || b->nbins <= 0 || b->nbins > ORC_MAXB) return -1;
+    if (p->level0 < 0 || p->rays_per_cell <= 0) return -1;
+    const int nb = b->nbins;
+    const int32_t nx = g->nx, ny = g->ny, nz = g->nz;
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    const double L = g->cell_cm, y = g->y_he;
+
+    /* Optical depth per cell length, per bin (section 2.2: all species). */
+    double* kappa = (double*)malloc((size_t)nb * (size_t)ncell * sizeof(double));
+    if (!kappa) return -1;
+    for (int64_t c = 0; c < ncell; ++c) {
+        const double nh = g->n_h[c], xhi = g->x_hi[c], xhei = g->x_hei[c], xheii = g->x_heii[c];
+        for (int k = 0; k < nb; ++k) {
+            const double* sg = b->sigma + 3 * k;
+            kappa[(int64_t)k * ncell + c] = L * nh * (sg[0] * xhi + y * (sg[1] * xhei + sg[2] * xheii));
+        }
+    }
+    memset(J, 0, (size_t)nb * (size_t)ncell * sizeof(double));
+    if (gdir) memset(gdir, 0, 3 * (size_t)ncell * sizeof(double));
+    memset(led, 0, sizeof(*led));
+
+    const int32_t lmax = p->max_level < 0 ? orc_auto_max_level(nx, ny, nz, p->rays_per_cell) : p->max_level;
+    const double tau_term = p->eps_term > 0 ? -log(p->eps_term) : INFINITY;
+    const double V = L * L * L;
+
+    stack_t_ st = {0, 0, 0};
+    for (int32_t src = 0; src < s->n; ++src) {
+        const double* xs = s->pos + 3 * src;
+        double S[ORC_MAXB];
+        for (int k = 0; k < nb; ++k) S[k] = s->ndot[src] * b->frac[k];
+        led->emitted += s->ndot[src];
+
+        ray_t root;
+        memset(&root, 0, sizeof(root));
+        root.level = p->level0;
+        for (int64_t q = orc_npix(p->level0) - 1; q >= 0; --q) {
+            root.pix = q;
+            if (push(&st, &root)) goto fail;
+        }
+        while (st.n > 0) {
+            const ray_t r = st.v[--st.n];
+            if (tree && led->tree_count < tree_cap)
+                tree[led->tree_count] = ((uint64_t)src << 32) | ((uint64_t)r.level << 28) | (uint64_t)r.pix;
+            led->tree_count++;
+            led->rays++;
+
+            double v[3], d[3];
+            orc_healpix_vec(r.level, r.pix, v);
+            for (int i = 0; i < 3; ++i) d[i] = (double)(float)v[i];
+            const double t0 = r.level == p->level0 ? 0.0 : orc_t_split(p->rays_per_cell, r.level - 1);
+            const double t_end = r.level < lmax ? orc_t_split(p->rays_per_cell, r.level) : INFINITY;
+
+            const double wray = 1.0 / (double)orc_npix(r.level);
+            double P[ORC_MAXB], tau[ORC_MAXB], dtau[ORC_MAXB];
+            for (int k = 0; k < nb; ++k) {
+                tau[k] = r.tau[k];
+                P[k] = S[k] * wray * exp(-tau[k]);
+            }
+            walk_t w;
+            if (!walk_start(&w, xs, d, t0, t_end, nx, ny, nz)) {
+                for (int k = 0; k < nb; ++k) led->escaped += P[k];
+                led->escaped_rays++;
+                continue;
+            }
+            for (;;) {
+                int at_end, mask;
+                const double tn = walk_next(&w, &at_end, &mask);
+                const double ds = tn - w.t;
+                const int64_t c = w.c[0] + (int64_t)nx * (w.c[1] + (int64_t)ny * w.c[2]);
+                led->crossings++;
+                for (int k = 0; k < nb; ++k) {
+                    const double kap = kappa[(int64_t)k * ncell + c];
+                    dtau[k] = kap * ds;
+                    const double lost = -expm1(-dtau[k]);        /* 1 - e^-dtau */
+                    J[(int64_t)k * ncell + c] += P[k] * ds * mean_atten(dtau[k]);
+                    led->absorbed_trace += P[k] * lost;
+                    if (gdir && dtau[k] > 0) {
+                        /* eq:ion with the absorbed photons split by species optical depth */
+                        const double nh = g->n_h[c];
+                        const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
+                        for (int sp = 0; sp < 3; ++sp) {
+                            if (ns_[sp] <= 0) continue;
+                            const double dts = L * ns_[sp] * b->sigma[3 * k + sp] * ds;
+                            gdir[(int64_t)sp * ncell + c] += P[k] * lost * (dts / dtau[k]) / (V * ns_[sp]);
+                        }
+                    }
+                    P[k] *= exp(-dtau[k]);
+                    tau[k] += dtau[k];
+                }
+                int term = tau_term < INFINITY;
+                for (int k = 0; k < nb && term; ++k)
+                    term = tau[k] >= tau_term && dtau[k] >= ORC_DTAU_TERM_MIN;
+                if (term) {
+                    for (int k = 0; k < nb; ++k) {
+                        const double kap = kappa[(int64_t)k * ncell + c];
+                        J[(int64_t)k * ncell + c] += P[k] / kap;
+                        led->absorbed_trace += P[k];
+                        if (gdir) {
+                            const double nh = g->n_h[c];
+                            const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
+                            for (int sp = 0; sp < 3; ++sp) {
+                                if (ns_[sp] <= 0) continue;
+                                const double ks = L * ns_[sp] * b->sigma[3 * k + sp];
+                                gdir[(int64_t)sp * ncell + c] += P[k] * (ks / kap) / (V * ns_[sp]);
+                            }
+                        }
+                    }
+                    led->terminated++;
+                    break;
+                }
+                if (at_end) {
+                    ray_t child;
+                    memset(&child, 0, sizeof(child));
+                    child.level = r.level + 1;
+                    for (int k = 0; k < nb; ++k) child.tau[k] = tau[k];
+                    for (int q = 3; q >= 0; --q) {
+                        child.pix = 4 * r.pix + q;
+                        if (push(&st, &child)) goto fail;
+                    }
+                    led->splits++;
+                    break;
+                }
+                walk_advance(&w, mask, tn);
+                if (!walk_inside(&w, nx, ny, nz)) {
+                    for (int k = 0; k < nb; ++k) led->escaped += P[k];
+                    led->escaped_rays++;
+                    break;
+                }
+            }
+        }
+    }
+    free(st.v);
+    free(kappa);
+    return 0;
+fail:
+    free(st.v);
+    free(kappa);
+    return -1;
+}
+
+void orc_finalize(const orc_grid* g, const orc_bins* b, const double* J, double* gamma, double* heat,
+                  double* absorbed)
+{
+    const int nb = b->nbins;
+    const int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+    const double L = g->cell_cm, y = g->y_he;
+    double total = 0;
+    for (int64_t c = 0; c < ncell; ++c) {
+        double gm[3] = {0, 0, 0}, ht[3] = {0, 0, 0};
+        const double nh = g->n_h[c];
+        for (int k = 0; k < nb; ++k) {
+            const double Jk = J[(int64_t)k * ncell + c];
+            const double* sg = b->sigma + 3 * k;
+            for (int sp = 0; sp < 3; ++sp) {
+                gm[sp] += sg[sp] * Jk / (L * L);
+                const double excess = b->e_erg[k] - b->e_thr[sp];
+                if (excess > 0) ht[sp] += sg[sp] * excess * Jk / (L * L);
+            }
+            const double kap = L * nh * (sg[0] * g->x_hi[c] + y * (sg[1] * g->x_hei[c] + sg[2] * g->x_heii[c]));
+            total += Jk * kap;
+        }
+        for (int sp = 0; sp < 3; ++sp) {
+            if (gamma) gamma[(int64_t)sp * ncell + c] = gm[sp];
+            if (heat) heat[(int64_t)sp * ncell + c] = ht[sp];
+        }
+    }
+    if (absorbed) *absorbed = total;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Chemistry.                                                                       */
+/* ------------------------------------------------------------------------------ */
+
+/* Hui & Gnedin (1997, MNRAS 292, 27), appendix fits, with lambda = 2 T_i / T. */
+static const double T_HI_K = 157807.0, T_HEI_K = 285335.0, T_HEII_K = 631515.0;
+
+void orc_rate_coeffs(double T, double out[6])
+{
+    const double lhi = 2.0 * T_HI_K / T, lhei = 2.0 * T_HEI_K / T, lheii = 2.0 * T_HEII_K / T;
+    /* case-B radiative recombination */
+    out[0] = 2.753e-14 * pow(lhi, 1.5) / pow(1.0 + pow(lhi / 2.740, 0.407), 2.242);
+    const double diel = 1.90e-3 * pow(T, -1.5) * exp(-0.75 * lheii / 2.0) * (1.0 + 0.3 * exp(-0.15 * lheii / 2.0));
+    out[1] = 1.26e-14 * pow(lhei, 0.750) + diel;
+    out[2] = 2.0 * 2.753e-14 * pow(lheii, 1.5) / pow(1.0 + pow(lheii / 2.740, 0.407), 2.242);
+    /* collisional ionisation */
+    out[3] = 21.11 * pow(T, -1.5) * exp(-lhi / 2.0) * pow(lhi, -1.089) / pow(1.0 + pow(lhi / 0.354, 0.874), 1.101);
+    out[4] = 32.38 * pow(T, -1.5) * exp(-lhei / 2.0) * pow(lhei, -1.146) / pow(1.0 + pow(lhei / 0.416, 0.987), 1.056);
+    out[5] = 19.95 * pow(T, -1.5) * exp(-lheii / 2.0) * pow(lheii, -1.089) / pow(1.0 + pow(lheii / 0.553, 0.735), 1.275);
+}
+
+/* Cooling rate per volume [erg cm^-3 s^-1]: recombination, collisional ionisation,
+ * collisional excitation and bremsstrahlung (section 2.8; Hui & Gnedin 1997). The
+ * Hubble-expansion and Compton terms need a cosmology and are not included. */
+static double cooling_rate(double T, double ne, double nhi, double nhii, double nhei, double nheii,
+                           double nheiii, int collisional)
+{
+    const double lhi = 2.0 * T_HI_K / T, lhei = 2.0 * T_HEI_K / T, lheii = 2.0 * T_HEII_K / T;
+    double k[6];
+    orc_rate_coeffs(T, k);
+    const double rec_hii = 3.435e-30 * T * pow(lhi, 1.970) / pow(1.0 + pow(lhi / 2.250, 0.376), 3.720);
+    const double rec_heii = KB_ERG * T * 1.26e-14 * pow(lhei, 0.750);
+    const double rec_heiii = 8.0 * 3.435e-30 * T * pow(lheii, 1.970) / pow(1.0 + pow(lheii / 2.250, 0.376), 3.720);
+    const double diel = 1.90e-3 * pow(T, -1.5) * exp(-0.75 * lheii / 2.0) * (1.0 + 0.3 * exp(-0.15 * lheii / 2.0));
+    const double diel_cool = 0.75 * 54.418 * EV_ERG * diel;
+    double lam = ne * (rec_hii * nhii + rec_heii * nheii + rec_heiii * nheiii + diel_cool * nheii);
+    if (collisional)
+        lam += ne * (13.598 * EV_ERG * k[3] * nhi + 24.587 * EV_ERG * k[4] * nhei + 54.418 * EV_ERG * k[5] * nheii);
+    const double damp = 1.0 + sqrt(T / 1e5);
+    lam += ne * nhi * 7.5e-19 * exp(-0.75 * lhi / 2.0) / damp;
+    lam += ne * nheii * 5.54e-17 * pow(T, -0.397) * exp(-0.75 * lheii / 2.0) / damp;
+    const double lt = log10(T);
+    const double gff = 1.1 + 0.34 * exp(-(5.5 - lt) * (5.5 - lt) / 3.0);
+    lam += 1.42e-27 * gff * sqrt(T) * (nhii + nheii + 4.0 * nheiii) * ne;
+    return lam;
+}
+
+void orc_chem(int64_t ncell, double y_he, const float* n_h, const float* x_hi, const float* x_hei,
+              const float* x_heii, const float* temp, const double* gamma, const double* heat, double dt,
+              const orc_chem_params* cp, double* x_hi_out, double* x_hei_out, double* x_heii_out,
+              double* temp_out, int32_t* nsub, int32_t* flags)
+{
+    for (int64_t c = 0; c < ncell; ++c) {
+        const double nh = n_h[c], nhe = y_he * nh;
+        double nhi = nh * (double)x_hi[c], nhii = nh - nhi;
+        double nhei = nhe * (double)x_hei[c], nheii = nhe * (double)x_heii[c];
+        double nheiii = nhe - nhei - nheii;
+        if (nheiii < 0) nheiii = 0;
+        double T = temp[c];
+        double ne = nhii + nheii + 2.0 * nheiii;
+        double E = 1.5 * KB_ERG * T * (nh + nhe + ne);
+        const double ghi = gamma[c], ghei = gamma[ncell + c], gheii = gamma[2 * ncell + c];
+        const double hhi = heat[c], hhei = heat[ncell + c], hheii = heat[2 * ncell + c];
+        double t = 0;
+        int32_t n = 0, flag = 0;
+        while (t < dt) {
+            double a_hii, a_heii = 0, a_heiii = 0, k_hi = 0, k_hei = 0, k_heii = 0;
+            if (cp->rates == 0) {
+                a_hii = cp->alpha_hii;
+            } else {
+                double k[6];
+                orc_rate_coeffs(T, k);
+                a_hii = k[0];
+                a_heii = k[1];
+                a_heiii = k[2];
+                if (cp->collisional) {
+                    k_hi = k[3];
+                    k_hei = k[4];
+                    k_heii = k[5];
+                }
+            }
+            /* eq:diffeq for HI */
+            const double ndot_hi = a_hii * ne * nhii - (ghi + k_hi * ne) * nhi;
+            double edot = 0;
+            if (!cp->isothermal)
+                edot = nhi * hhi + nhei * hhei + nheii * hheii -
+                       cooling_rate(T, ne, nhi, nhii, nhei, nheii, nheiii, cp->collisional);
+            /* sub-cycle step: limit the fractional change of E and n_HI to eps */
+            double h = dt - t;
+            int last = 1;
+            if (n >= cp->max_sub) {
+                flag = 1;
+            } else {
+                if (edot != 0 && cp->eps * E / fabs(edot) < h) {
+                    h = cp->eps * E / fabs(edot);
+                    last = 0;
+                }
+                /* both hydrogen states are tracked quantities: limit the fractional change
+                 * of n_HI and of n_HII (a cell that starts fully ionised or fully neutral
+                 * would otherwise take one unbounded explicit source step) */
+                if (nhi > 0 && ndot_hi != 0 && cp->eps * nhi / fabs(ndot_hi) < h) {
+                    h = cp->eps * nhi / fabs(ndot_hi);
+                    last = 0;
+                }
+                if (nhii > 0 && ndot_hi != 0 && cp->eps * nhii / fabs(ndot_hi) < h) {
+                    h = cp->eps * nhii / fabs(ndot_hi);
+                    last = 0;
+                }
+            }
+            /* eq:anninos, backward difference n' = (n + D h) / (1 + C h), in the order
+             * HI, HeI, HeIII, with HeII from helium conservation */
+            nhi = (nhi + a_hii * ne * nhii * h) / (1.0 + (ghi + k_hi * ne) * h);
+            if (nhi > nh) nhi = nh;
+            nhii = nh - nhi;
+            double nhei_new = (nhei + a_heii * ne * nheii * h) / (1.0 + (ghei + k_hei * ne) * h);
+            double nheiii_new = (nheiii + (gheii + k_heii * ne) * nheii * h) / (1.0 + a_heiii * ne * h);
+            if (nhei_new > nhe) nhei_new = nhe;
+            if (nheiii_new > nhe - nhei_new) nheiii_new = nhe - nhei_new;
+            nhei = nhei_new;
+            nheiii = nheiii_new;
+            nheii = nhe - nhei - nheiii;
+            if (nheii < 0) nheii = 0;
+            ne = nhii + nheii + 2.0 * nheiii;
+            if (!cp->isothermal) {
+                E += edot * h;
+                T = E / (1.5 * KB_ERG * (nh + nhe + ne));
+                if (T < cp->t_floor) {
+                    T = cp->t_floor;
+                    E = 1.5 * KB_ERG * T * (nh + nhe + ne);
+                }
+            }
+            t = last ? dt : t + h;
+            ++n;
+        }
+        x_hi_out[c] = nhi / nh;
+        x_hei_out[c] = nhe > 0 ? nhei / nhe : (double)x_hei[c];
+        x_heii_out[c] = nhe > 0 ? nheii / nhe : (double)x_heii[c];
+        temp_out[c] = T;
+        if (nsub) nsub[c] = n;
+        if (flags) flags[c] = flag;
+    }
+}
