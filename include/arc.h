@@ -1,0 +1,188 @@
+/*
+ * arc.h -- C ABI of libarc, the gfx950 (MI355X) implementation of the adaptive HEALPix
+ * ray-tracing radiative-transfer step of Hartley & Ricotti, "ARC: Adaptive
+ * Ray-tracing with CUDA" (arXiv:1807.07094).
+ *
+ * One call to arc_trace casts rays from every point source through a uniform grid
+ * (section 2.1, steps iii a-d; section 2.4), splits each ray into four HEALPix
+ * children when its cross-section outgrows the cell, attenuates the photons of every
+ * frequency bin by exp(-tau) at each cell crossing and deposits the photons lost in a
+ * cell there (eq:ion, photon conserving), and returns per-cell photoionisation and
+ * photoheating rates for HI, HeI and HeII (eq:ion with the in-bin species split;
+ * section 2.8). arc_chem_step then advances each cell's ionisation state and
+ * temperature (eq:diffeq, eq:anninos, section 2.7).
+ *
+ * Conventions
+ *   - Every call returns an arc_status. No exception or abort crosses this ABI.
+ *   - Grid arrays are device pointers owned by the caller, FP32, contiguous, laid out
+ *     [nz][ny][nx] with x fastest. Positions and lengths are in cell units.
+ *   - Source and bin tables are host pointers owned by the caller; they are read
+ *     during the call only.
+ *   - The context owns every internal buffer (opacity, fixed-point radiation field,
+ *     ray queues, direction tables). One context per host thread.
+ *   - Calls are blocking: they enqueue on the given stream (NULL = the default stream),
+ *     then synchronise it before returning.
+ *   - After ARC_E_DEVICE the context must be destroyed. After any other error it stays
+ *     usable, and the contents of the outputs are unspecified.
+ */
+#ifndef ARC_H
+#define ARC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t arc_status;
+#define ARC_OK 0
+#define ARC_E_ARG (-1)         /* null pointer, bad size or bad enum */
+#define ARC_E_RANGE (-2)       /* value outside its domain: source off-grid or off the 2^-12
+                                  lattice, n_H <= 0, a fraction outside [0,1], non-finite
+                                  input, a bin with sigma_HI <= 0 */
+#define ARC_E_NOMEM (-3)       /* device allocation failed */
+#define ARC_E_DEVICE (-4)      /* HIP runtime error; destroy the context */
+#define ARC_E_OVERFLOW (-5)    /* requested fixed-point unit cannot hold the field */
+#define ARC_E_QUEUE (-6)       /* ray-queue capacity exceeded */
+#define ARC_E_UNSUPPORTED (-7) /* valid but not implemented combination */
+
+typedef struct arc_ctx arc_ctx;
+
+/* Create a context on HIP device `device`. */
+arc_status arc_create(int32_t device, arc_ctx** out);
+/* Release every buffer the context owns. NULL is ignored. */
+void arc_destroy(arc_ctx* ctx);
+/* Text of the last error on this context (never NULL; "" after success). */
+const char* arc_last_error(const arc_ctx* ctx);
+
+/* Uniform N^3 grid (section 2.3). Device pointers, caller-owned. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double cell_cm;     /* cell side L [cm] */
+    double y_he;        /* n_He / n_H by number; 0 = hydrogen only */
+    const float* n_h;   /* [ncell] hydrogen number density [cm^-3], > 0 */
+    float* x_hi;        /* [ncell] n_HI / n_H in [0,1] */
+    float* x_hei;       /* [ncell] n_HeI / n_He in [0,1] */
+    float* x_heii;      /* [ncell] n_HeII / n_He in [0,1] */
+    float* temp;        /* [ncell] temperature [K] (read and written by arc_chem_step) */
+} arc_grid;
+
+/* Point sources (section 2.1: source positions; section 2.4: photon rate per bin).
+ * Host pointers. Positions must lie on the 2^-12 cell lattice inside [0, n). */
+typedef struct {
+    int32_t n;
+    const double* pos;  /* [n][3] x, y, z in cell units */
+    const double* ndot; /* [n] ionising photons per second, escape fraction applied */
+} arc_sources;
+
+/* Frequency bins (section 2.2): one frequency per bin standing for the bin-averaged
+ * cross sections. Host pointers. 1 <= nbins <= 4. */
+typedef struct {
+    int32_t nbins;
+    const double* frac;  /* [nbins] fraction of each source's photons in the bin, sum 1 */
+    const double* e_erg; /* [nbins] photon energy [erg] */
+    const double* sigma; /* [nbins][3] cross sections of HI, HeI, HeII [cm^2]; HI > 0 */
+    const double* e_thr; /* [3] ionisation thresholds of HI, HeI, HeII [erg] */
+} arc_freq_bins;
+
+/* Arithmetic of the traversal (section 2.4 stepping and attenuation). */
+#define ARC_PREC_FP32_COMP 0  /* FP32 with double-float path length and compensated tau */
+#define ARC_PREC_FP32_PLAIN 1 /* FP32 with plain path length and tau sums */
+
+/* Work schedule. Both give bitwise-identical fixed-point fields for the same precision. */
+#define ARC_SCHED_PLAIN 0     /* per source, per HEALPix level launches (section 2.1 iii) */
+#define ARC_SCHED_BATCHED 1   /* every source in one persistent launch with a device queue */
+
+typedef struct {
+    int32_t level0;        /* HEALPix level of the root rays (section 2.1: typically 1) */
+    int32_t max_level;     /* last level that splits; < 0 = first level whose split radius
+                              reaches the box diagonal */
+    double rays_per_cell;  /* Phi: rays per cell-face area at the split radius (> 0) */
+    double eps_term;       /* a ray ends once every bin is attenuated below eps_term (and
+                              its last crossing had dtau >= 0.01 in every bin); the rest of
+                              its photons are absorbed in that cell. 0 = never. */
+    int32_t precision;     /* ARC_PREC_* */
+    int32_t schedule;      /* ARC_SCHED_* */
+    void* stream;          /* hipStream_t, NULL = default stream */
+    int32_t tune_waves;    /* batched: waves per workgroup (0 = default) */
+    int32_t tune_blocks;   /* batched: workgroups in the persistent grid (0 = default) */
+    int32_t tune_refill;   /* batched: refill a wave once this many lanes idle (0 = default) */
+    int32_t tune_item_level; /* batched: HEALPix level whose rays become the persistent
+                                launch's work items; earlier levels are traced level by
+                                level (0 = first level with 16 items per wave) */
+    uint64_t* tree_out;    /* optional device array: every ray traced is appended as
+                              (src << 32) | (level << 28) | pixel; NULL = off */
+    int64_t tree_cap;      /* capacity of tree_out in entries */
+    double u_j_override;   /* 0 = automatic fixed-point unit; > 0 forces this unit (tests) */
+} arc_trace_params;
+
+/* Rates out: device pointers, caller-owned, each [3][ncell] (HI, HeI, HeII). */
+typedef struct {
+    float* gamma;  /* photoionisation rate per absorber [1/s] */
+    float* heat;   /* photoheating rate per absorber [erg/s] */
+} arc_rates;
+
+/* Photon ledger of one trace, in photons emitted during dt (rates times dt). */
+typedef struct {
+    double emitted;        /* sum over sources of ndot * dt */
+    double absorbed;       /* sum over cells and bins of deposited-field * opacity * dt */
+    double escaped;        /* photons carried out of the grid */
+    uint64_t crossings;    /* (ray, cell) segments: the unit of the throughput metric */
+    uint64_t rays;         /* rays traced */
+    uint64_t splits;       /* rays split into four children */
+    uint64_t terminated;   /* rays ended by the attenuation criterion */
+    uint64_t escaped_rays; /* rays that left the grid */
+    uint64_t spills;       /* batched: ray records moved from on-chip queues to memory */
+    int64_t tree_count;    /* rays appended to tree_out (may exceed tree_cap) */
+    double u_j[4];         /* fixed-point unit of each bin [photons/s * cell] */
+    double ms_trace;       /* device time of the trace kernels [ms] */
+    double ms_total;       /* device time of the whole call [ms] */
+} arc_ledger;
+
+/* One ray-tracing pass (a whole RT step's radiation field). `out` receives the rates;
+ * `ledger` may be NULL. dt > 0 only scales the ledger. */
+arc_status arc_trace(arc_ctx* ctx, const arc_grid* grid, const arc_sources* src,
+                     const arc_freq_bins* bins, double dt, const arc_trace_params* params,
+                     arc_rates* out, arc_ledger* ledger);
+
+/* Copy the fixed-point field of the last arc_trace, [nbins][ncell] int64 in units of
+ * ledger.u_j[b], into the device array `dst` (caller-owned, nbins * ncell entries). */
+arc_status arc_get_field(arc_ctx* ctx, int64_t* dst, int64_t count, void* stream);
+
+/* FP32 HEALPix pixel centres of `level` (nested order) as used by the tracer, written
+ * to the device array `dst` of 3 * 12 * 4^level floats (x, y, z per pixel). */
+arc_status arc_healpix_dirs(arc_ctx* ctx, int32_t level, float* dst, void* stream);
+
+/* Chemistry (section 2.7 and 2.8). */
+#define ARC_CHEM_PLAIN 0
+
+typedef struct {
+    int32_t isothermal;    /* 1: temperature fixed */
+    int32_t rates;         /* 0: fixed alpha_hii, no helium recombination or collisional
+                              terms; 1: Hui & Gnedin (1997) case-B coefficients and cooling */
+    int32_t collisional;   /* include collisional ionisation (rates == 1) */
+    double alpha_hii;      /* [cm^3/s] for rates == 0 */
+    double eps;            /* sub-cycle limit on fractional changes (paper: 0.1) */
+    int32_t max_sub;       /* sub-cycle cap, then one backward step to the end */
+    double t_floor;        /* minimum temperature [K] */
+    int32_t mode;          /* ARC_CHEM_* */
+    void* stream;          /* hipStream_t, NULL = default stream */
+} arc_chem_params;
+
+typedef struct {
+    int64_t cells;         /* cells updated */
+    int64_t sub_total;     /* sub-cycles summed over cells */
+    int32_t sub_max;       /* largest sub-cycle count of a cell */
+    int64_t capped;        /* cells that reached max_sub */
+    double ms;             /* device time [ms] */
+} arc_chem_stats;
+
+/* Advance x_hi, x_hei, x_heii and temp of `grid` in place over dt [s] with the rates
+ * held constant. `stats` may be NULL. */
+arc_status arc_chem_step(arc_ctx* ctx, const arc_grid* grid, const arc_rates* rates, double dt,
+                         const arc_chem_params* params, arc_chem_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,209 @@
+"""ctypes binding of libarc (include/arc.h). Argument marshalling only: every step of the
+ray-tracing and chemistry path runs in the HIP kernels of the library.
+
+Device arrays are passed as torch CUDA tensors (their data pointers); host tables as
+numpy arrays. The library must have been built (``python -m paper_1807_07094_amd.build``);
+loading fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_build", "libarc.so")
+_lib = None
+
+ARC_OK = 0
+STATUS = {0: "ARC_OK", -1: "ARC_E_ARG", -2: "ARC_E_RANGE", -3: "ARC_E_NOMEM", -4: "ARC_E_DEVICE",
+          -5: "ARC_E_OVERFLOW", -6: "ARC_E_QUEUE", -7: "ARC_E_UNSUPPORTED"}
+PREC = {"fp32_comp": 0, "fp32_plain": 1}
+SCHED = {"plain": 0, "batched": 1}
+
+
+class ArcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("cell_cm", C.c_double),
+                ("y_he", C.c_double), ("n_h", C.c_void_p), ("x_hi", C.c_void_p), ("x_hei", C.c_void_p),
+                ("x_heii", C.c_void_p), ("temp", C.c_void_p)]
+
+
+class Sources(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pos", C.c_void_p), ("ndot", C.c_void_p)]
+
+
+class Bins(C.Structure):
+    _fields_ = [("nbins", C.c_int32), ("frac", C.c_void_p), ("e_erg", C.c_void_p), ("sigma", C.c_void_p),
+                ("e_thr", C.c_void_p)]
+
+
+class TraceParams(C.Structure):
+    _fields_ = [("level0", C.c_int32), ("max_level", C.c_int32), ("rays_per_cell", C.c_double),
+                ("eps_term", C.c_double), ("precision", C.c_int32), ("schedule", C.c_int32),
+                ("stream", C.c_void_p), ("tune_waves", C.c_int32), ("tune_blocks", C.c_int32),
+                ("tune_refill", C.c_int32), ("tune_item_level", C.c_int32), ("tree_out", C.c_void_p),
+                ("tree_cap", C.c_int64), ("u_j_override", C.c_double)]
+
+
+class Rates(C.Structure):
+    _fields_ = [("gamma", C.c_void_p), ("heat", C.c_void_p)]
+
+
+class Ledger(C.Structure):
+    _fields_ = [("emitted", C.c_double), ("absorbed", C.c_double), ("escaped", C.c_double),
+                ("crossings", C.c_uint64), ("rays", C.c_uint64), ("splits", C.c_uint64),
+                ("terminated", C.c_uint64), ("escaped_rays", C.c_uint64), ("spills", C.c_uint64),
+                ("tree_count", C.c_int64), ("u_j", C.c_double * 4), ("ms_trace", C.c_double),
+                ("ms_total", C.c_double)]
+
+
+class ChemParams(C.Structure):
+    _fields_ = [("isothermal", C.c_int32), ("rates", C.c_int32), ("collisional", C.c_int32),
+                ("alpha_hii", C.c_double), ("eps", C.c_double), ("max_sub", C.c_int32), ("t_floor", C.c_double),
+                ("mode", C.c_int32), ("stream", C.c_void_p)]
+
+
+class ChemStats(C.Structure):
+    _fields_ = [("cells", C.c_int64), ("sub_total", C.c_int64), ("sub_max", C.c_int32), ("capped", C.c_int64),
+                ("ms", C.c_double)]
+
+
+def lib():
+    """Load libarc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"libarc.so not built ({_LIB_PATH}); run python -m paper_1807_07094_amd.build")
+        L = C.CDLL(_LIB_PATH)
+        L.arc_create.restype = C.c_int32
+        L.arc_create.argtypes = [C.c_int32, C.POINTER(C.c_void_p)]
+        L.arc_destroy.restype = None
+        L.arc_destroy.argtypes = [C.c_void_p]
+        L.arc_last_error.restype = C.c_char_p
+        L.arc_last_error.argtypes = [C.c_void_p]
+        L.arc_trace.restype = C.c_int32
+        L.arc_trace.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Sources), C.POINTER(Bins), C.c_double,
+                                C.POINTER(TraceParams), C.POINTER(Rates), C.POINTER(Ledger)]
+        L.arc_get_field.restype = C.c_int32
+        L.arc_get_field.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.arc_healpix_dirs.restype = C.c_int32
+        L.arc_healpix_dirs.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.arc_chem_step.restype = C.c_int32
+        L.arc_chem_step.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Rates), C.c_double,
+                                    C.POINTER(ChemParams), C.POINTER(ChemStats)]
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        if not t.is_contiguous():
+            raise ValueError("device arrays must be contiguous")
+        return C.c_void_p(t.data_ptr())
+    return t.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def device_grid(grid: dict, device="cuda"):
+    """Copy a workload grid (numpy float32 arrays) to the device as torch tensors."""
+    import torch
+
+    out = {k: torch.from_numpy(np.ascontiguousarray(grid[k], np.float32)).to(device)
+           for k in ("n_h", "x_hi", "x_hei", "x_heii", "temp") if k in grid}
+    out["cell_cm"] = float(grid["cell_cm"])
+    out["y_he"] = float(grid["y_he"])
+    return out
+
+
+def _grid(g) -> Grid:
+    nz, ny, nx = g["n_h"].shape
+    for k in ("n_h", "x_hi", "x_hei", "x_heii", "temp"):
+        if k in g and tuple(g[k].shape) != (nz, ny, nx):
+            raise ValueError(f"grid array {k} has shape {tuple(g[k].shape)}, expected {(nz, ny, nx)}")
+    return Grid(nx, ny, nz, float(g["cell_cm"]), float(g["y_he"]), _ptr(g["n_h"]), _ptr(g["x_hi"]),
+                _ptr(g["x_hei"]), _ptr(g["x_heii"]), _ptr(g.get("temp")))
+
+
+class Context:
+    """An arc_ctx: owns the library's device buffers on one GPU."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        rc = lib().arc_create(device, C.byref(h))
+        if rc != ARC_OK:
+            raise ArcError(rc, "arc_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().arc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != ARC_OK:
+            raise ArcError(rc, lib().arc_last_error(self._h).decode())
+
+    def trace(self, grid, sources: dict, bins: dict, dt: float, gamma, heat, level0=1, rays_per_cell=4.0,
+              max_level=-1, eps_term=1e-6, precision="fp32_comp", schedule="batched", stream=None, tree=None,
+              tune_waves=0, tune_blocks=0, tune_refill=0, tune_item_level=0, u_j_override=0.0) -> dict:
+        """arc_trace. gamma/heat: device float32 tensors of shape [3, nz, ny, nx]."""
+        g = _grid(grid)
+        pos = np.ascontiguousarray(sources["pos"], np.float64).reshape(-1, 3)
+        ndot = np.ascontiguousarray(sources["ndot"], np.float64).reshape(-1)
+        frac = np.ascontiguousarray(bins["frac"], np.float64)
+        e = np.ascontiguousarray(bins["e_erg"], np.float64)
+        sig = np.ascontiguousarray(bins["sigma"], np.float64).reshape(-1, 3)
+        thr = np.ascontiguousarray(bins["e_thr"], np.float64)
+        s = Sources(ndot.size, _ptr(pos), _ptr(ndot))
+        b = Bins(frac.size, _ptr(frac), _ptr(e), _ptr(sig), _ptr(thr))
+        p = TraceParams(int(level0), int(max_level), float(rays_per_cell), float(eps_term),
+                        PREC[precision] if isinstance(precision, str) else int(precision),
+                        SCHED[schedule] if isinstance(schedule, str) else int(schedule), _stream(stream),
+                        int(tune_waves), int(tune_blocks), int(tune_refill), int(tune_item_level), _ptr(tree),
+                        int(tree.numel()) if tree is not None else 0, float(u_j_override))
+        r = Rates(_ptr(gamma), _ptr(heat))
+        led = Ledger()
+        self._check(lib().arc_trace(self._h, C.byref(g), C.byref(s), C.byref(b), float(dt), C.byref(p),
+                                    C.byref(r), C.byref(led)))
+        out = {k: getattr(led, k) for k, _ in Ledger._fields_ if k != "u_j"}
+        out["u_j"] = list(led.u_j)
+        return out
+
+    def get_field(self, dst, stream=None):
+        """arc_get_field into a device int64 tensor of nbins * ncell entries."""
+        self._check(lib().arc_get_field(self._h, _ptr(dst), int(dst.numel()), _stream(stream)))
+        return dst
+
+    def healpix_dirs(self, level: int, dst, stream=None):
+        self._check(lib().arc_healpix_dirs(self._h, int(level), _ptr(dst), _stream(stream)))
+        return dst
+
+    def chem_step(self, grid, gamma, heat, dt: float, isothermal=0, rates=1, collisional=1, alpha_hii=2.59e-13,
+                  eps=0.1, max_sub=100000, t_floor=1.0, mode=0, stream=None) -> dict:
+        g = _grid(grid)
+        r = Rates(_ptr(gamma), _ptr(heat))
+        p = ChemParams(int(isothermal), int(rates), int(collisional), float(alpha_hii), float(eps), int(max_sub),
+                       float(t_floor), int(mode), _stream(stream))
+        st = ChemStats()
+        self._check(lib().arc_chem_step(self._h, C.byref(g), C.byref(r), float(dt), C.byref(p), C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ChemStats._fields_}

@@ -1,0 +1,609 @@
+// arc_api.hip -- host side of libarc: the C ABI of include/arc.h.
+//
+// Validation, fixed-point unit selection, buffer ownership and the two tracing
+// schedules. Every per-cell and per-ray step runs in the kernels of arc_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "arc.h"
+#include "arc_kernels.h"
+
+using namespace arc;
+
+struct arc_ctx {
+    int device = 0;
+    int cus = 0;
+    std::string err;
+    // grid-sized buffers
+    size_t ncell_cap = 0;
+    int nbp_cap = 0;
+    void* kappa = nullptr;             // float or float4 per cell
+    size_t kappa_bytes = 0;
+    unsigned long long* J = nullptr;   // [cell][nbp]
+    size_t J_bytes = 0;
+    // source table
+    SourceRec* src = nullptr;
+    double* src_pos = nullptr;
+    double* src_ndot = nullptr;
+    int src_cap = 0;
+    // HEALPix centres, levels 0..dirs_levels-1
+    float4* dirs = nullptr;
+    int dirs_levels = 0;
+    long long dir_off[kMaxLevels] = {0};
+    // ray arrays (per-level schedule) and work queue (batched)
+    RayRec* rays[2] = {nullptr, nullptr};
+    size_t rays_cap = 0;
+    RayRec* spill = nullptr;
+    size_t spill_entries = 0;
+    // small device scalars
+    unsigned long long* counters = nullptr;  // kNumCounters
+    double* acc = nullptr;                    // [0..3] escaped per bin, [4] absorbed
+    uint32_t* u32 = nullptr;                  // [0] n_out, [1] queue head
+    int* errflag = nullptr;
+    unsigned long long* chem_stats = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // last trace
+    int last_nb = 0, last_nbp = 0;
+    size_t last_ncell = 0;
+    bool have_field = false;
+};
+
+namespace {
+
+arc_status fail(arc_ctx* c, arc_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? ARC_E_NOMEM : ARC_E_DEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                        \
+    } while (0)
+
+template <typename T>
+hipError_t grow(T** p, size_t* cap_bytes, size_t need_bytes)
+{
+    if (*p && *cap_bytes >= need_bytes) return hipSuccess;
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        if (e != hipSuccess) return e;
+        *p = nullptr;
+        *cap_bytes = 0;
+    }
+    hipError_t e = hipMalloc((void**)p, need_bytes);
+    if (e == hipSuccess) *cap_bytes = need_bytes;
+    return e;
+}
+
+bool on_lattice(double v) { return std::isfinite(v) && std::floor(v * 4096.0) == v * 4096.0; }
+
+// Split radius of each level, rounded once to float (pi r^2 / (3 4^l) = 1 / Phi).
+float split_base(double phi) { return (float)std::sqrt(3.0 / (M_PI * phi)); }
+
+int auto_max_level(int nx, int ny, int nz, double phi)
+{
+    const double diag = std::sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
+    const float base = split_base(phi);
+    int l = 0;
+    while ((double)std::ldexp(base, l) < diag && l < 40) ++l;
+    return l;
+}
+
+arc_status check_grid(arc_ctx* c, const arc_grid* g)
+{
+    if (!g || !g->n_h || !g->x_hi || !g->x_hei || !g->x_heii) return fail(c, ARC_E_ARG, "null grid pointer");
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return fail(c, ARC_E_ARG, "grid dimensions must be positive");
+    if (g->nx > 2048 || g->ny > 2048 || g->nz > 2048)
+        return fail(c, ARC_E_UNSUPPORTED, "grid dimensions above 2048 are not supported");
+    const double ncell = (double)g->nx * g->ny * g->nz;
+    if (ncell > 2147483647.0) return fail(c, ARC_E_UNSUPPORTED, "more than 2^31-1 cells");
+    if (!(g->cell_cm > 0) || !std::isfinite(g->cell_cm)) return fail(c, ARC_E_RANGE, "cell_cm must be finite and > 0");
+    if (!(g->y_he >= 0) || !std::isfinite(g->y_he)) return fail(c, ARC_E_RANGE, "y_he must be finite and >= 0");
+    return ARC_OK;
+}
+
+arc_status check_bins(arc_ctx* c, const arc_freq_bins* b)
+{
+    if (!b || !b->frac || !b->e_erg || !b->sigma || !b->e_thr) return fail(c, ARC_E_ARG, "null bin pointer");
+    if (b->nbins < 1 || b->nbins > kMaxBins) return fail(c, ARC_E_ARG, "nbins must be 1..4");
+    double sum = 0;
+    for (int k = 0; k < b->nbins; ++k) {
+        if (!(b->frac[k] >= 0) || !std::isfinite(b->frac[k])) return fail(c, ARC_E_RANGE, "frac[%d] invalid", k);
+        if (!(b->e_erg[k] > 0) || !std::isfinite(b->e_erg[k])) return fail(c, ARC_E_RANGE, "e_erg[%d] invalid", k);
+        if (!(b->sigma[3 * k] > 0) || !std::isfinite(b->sigma[3 * k]))
+            return fail(c, ARC_E_RANGE, "sigma_HI of bin %d must be > 0", k);
+        for (int s = 1; s < 3; ++s)
+            if (!(b->sigma[3 * k + s] >= 0) || !std::isfinite(b->sigma[3 * k + s]))
+                return fail(c, ARC_E_RANGE, "sigma[%d][%d] invalid", k, s);
+        sum += b->frac[k];
+    }
+    if (std::fabs(sum - 1.0) > 1e-6) return fail(c, ARC_E_RANGE, "bin fractions sum to %.9g, not 1", sum);
+    for (int s = 0; s < 3; ++s)
+        if (!(b->e_thr[s] > 0) || !std::isfinite(b->e_thr[s])) return fail(c, ARC_E_RANGE, "e_thr[%d] invalid", s);
+    return ARC_OK;
+}
+
+arc_status check_sources(arc_ctx* c, const arc_sources* s, const arc_grid* g)
+{
+    if (!s) return fail(c, ARC_E_ARG, "null sources");
+    if (s->n < 0) return fail(c, ARC_E_ARG, "negative source count");
+    if (s->n > 0 && (!s->pos || !s->ndot)) return fail(c, ARC_E_ARG, "null source arrays");
+    const int dims[3] = {g->nx, g->ny, g->nz};
+    for (int i = 0; i < s->n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            const double v = s->pos[3 * i + a];
+            if (!on_lattice(v)) return fail(c, ARC_E_RANGE, "source %d coordinate %d is not on the 2^-12 lattice", i, a);
+            if (!(v >= 0.0 && v < (double)dims[a])) return fail(c, ARC_E_RANGE, "source %d lies outside the grid", i);
+        }
+        if (!(s->ndot[i] > 0) || !std::isfinite(s->ndot[i])) return fail(c, ARC_E_RANGE, "source %d ndot invalid", i);
+    }
+    return ARC_OK;
+}
+
+arc_status ensure_dirs(arc_ctx* c, int levels, hipStream_t st)
+{
+    if (levels <= c->dirs_levels) return ARC_OK;
+    long long off[kMaxLevels];
+    long long total = 0;
+    for (int l = 0; l < levels; ++l) {
+        off[l] = total;
+        total += 12ll << (2 * l);
+    }
+    float4* nd = nullptr;
+    HIP_TRY(c, hipMalloc((void**)&nd, (size_t)total * sizeof(float4)));
+    for (int l = 0; l < levels; ++l) {
+        hipError_t e = launch_healpix(l, nd + off[l], st);
+        if (e != hipSuccess) {
+            (void)hipFree(nd);
+            return fail(c, ARC_E_DEVICE, "healpix launch: %s", hipGetErrorString(e));
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (c->dirs) HIP_TRY(c, hipFree(c->dirs));
+    c->dirs = nd;
+    c->dirs_levels = levels;
+    for (int l = 0; l < levels; ++l) c->dir_off[l] = off[l];
+    return ARC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+arc_status arc_create(int32_t device, arc_ctx** out)
+{
+    if (!out) return ARC_E_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ARC_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return ARC_E_DEVICE;
+    arc_ctx* c = new (std::nothrow) arc_ctx();
+    if (!c) return ARC_E_NOMEM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return ARC_E_DEVICE;
+    }
+    c->cus = prop.multiProcessorCount;
+    bool ok = hipMalloc((void**)&c->counters, kNumCounters * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void**)&c->acc, 8 * sizeof(double)) == hipSuccess &&
+              hipMalloc((void**)&c->u32, 4 * sizeof(uint32_t)) == hipSuccess &&
+              hipMalloc((void**)&c->errflag, sizeof(int)) == hipSuccess &&
+              hipMalloc((void**)&c->chem_stats, 4 * sizeof(unsigned long long)) == hipSuccess;
+    for (int i = 0; i < 4 && ok; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
+    if (!ok) {
+        arc_destroy(c);
+        return ARC_E_NOMEM;
+    }
+    *out = c;
+    return ARC_OK;
+}
+
+void arc_destroy(arc_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    void* bufs[] = {c->kappa, c->J, c->src, c->src_pos, c->src_ndot, c->dirs, c->rays[0], c->rays[1],
+                    c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    for (int i = 0; i < 4; ++i)
+        if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    delete c;
+}
+
+const char* arc_last_error(const arc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const arc_freq_bins* b, double dt,
+                     const arc_trace_params* p, arc_rates* out, arc_ledger* ledger)
+{
+    if (!c) return ARC_E_ARG;
+    c->err.clear();
+    arc_status rc;
+    if ((rc = check_grid(c, g)) != ARC_OK) return rc;
+    if ((rc = check_bins(c, b)) != ARC_OK) return rc;
+    if ((rc = check_sources(c, s, g)) != ARC_OK) return rc;
+    if (!p) return fail(c, ARC_E_ARG, "null params");
+    if (!out || !out->gamma || !out->heat) return fail(c, ARC_E_ARG, "null rate outputs");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, ARC_E_RANGE, "dt must be finite and > 0");
+    if (!(p->rays_per_cell > 0) || !std::isfinite(p->rays_per_cell)) return fail(c, ARC_E_RANGE, "rays_per_cell must be > 0");
+    if (!(p->eps_term >= 0 && p->eps_term < 1)) return fail(c, ARC_E_RANGE, "eps_term must be in [0,1)");
+    if (p->precision != ARC_PREC_FP32_COMP && p->precision != ARC_PREC_FP32_PLAIN) return fail(c, ARC_E_ARG, "bad precision");
+    if (p->schedule != ARC_SCHED_PLAIN && p->schedule != ARC_SCHED_BATCHED) return fail(c, ARC_E_ARG, "bad schedule");
+    const int lmax = p->max_level < 0 ? auto_max_level(g->nx, g->ny, g->nz, p->rays_per_cell) : p->max_level;
+    if (p->level0 < 0 || p->level0 > lmax) return fail(c, ARC_E_ARG, "level0 must be in [0, max_level]");
+    if (lmax > 12) return fail(c, ARC_E_UNSUPPORTED, "max_level %d > 12 (pixel ids are 28-bit)", lmax);
+    if (!(p->u_j_override >= 0)) return fail(c, ARC_E_ARG, "u_j_override must be >= 0");
+    if (p->tree_out && p->tree_cap < 0) return fail(c, ARC_E_ARG, "tree_cap < 0");
+
+    hipStream_t st = (hipStream_t)p->stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int nb = b->nbins;
+    const int nbp = nb == 1 ? 1 : (nb == 2 ? 2 : 4);
+    const size_t ncell = (size_t)g->nx * g->ny * g->nz;
+
+    // Fixed-point unit per bin. One source deposits at most sqrt(3) S_b into a cell
+    // (the photon rate through any sphere is at most S_b and a cell is at most sqrt(3)
+    // long), plus a remainder below eps_term S_b sqrt(3) / 0.01 on termination. The sum
+    // over sources therefore stays below 2^62 units.
+    double uj[kMaxBins] = {1, 1, 1, 1};
+    double sum_ndot = 0;
+    for (int i = 0; i < s->n; ++i) sum_ndot += s->ndot[i];
+    for (int k = 0; k < nb; ++k) {
+        const double bound = (std::sqrt(3.0) + p->eps_term * std::sqrt(3.0) / (double)kDtauTermMin) * sum_ndot *
+                             b->frac[k] * (1.0 + 1e-6);
+        const double need = bound / 4611686018427387904.0;  // 2^62
+        if (p->u_j_override > 0) {
+            if (p->u_j_override < need)
+                return fail(c, ARC_E_OVERFLOW, "fixed-point unit %.6g too small for bin %d (needs >= %.6g)",
+                            p->u_j_override, k, need);
+            uj[k] = p->u_j_override;
+        } else {
+            uj[k] = need > 0 ? need : 1.0;
+        }
+    }
+
+    // Buffers.
+    {
+        const size_t kb = ncell * (nb == 1 ? sizeof(float) : sizeof(float4));
+        HIP_TRY(c, grow(&c->kappa, &c->kappa_bytes, kb));
+        HIP_TRY(c, grow(&c->J, &c->J_bytes, ncell * nbp * sizeof(unsigned long long)));
+        if (s->n > c->src_cap) {
+            if (c->src) HIP_TRY(c, hipFree(c->src));
+            if (c->src_pos) HIP_TRY(c, hipFree(c->src_pos));
+            if (c->src_ndot) HIP_TRY(c, hipFree(c->src_ndot));
+            c->src = nullptr;
+            c->src_pos = c->src_ndot = nullptr;
+            c->src_cap = 0;
+            HIP_TRY(c, hipMalloc((void**)&c->src, s->n * sizeof(SourceRec)));
+            HIP_TRY(c, hipMalloc((void**)&c->src_pos, s->n * 3 * sizeof(double)));
+            HIP_TRY(c, hipMalloc((void**)&c->src_ndot, s->n * sizeof(double)));
+            c->src_cap = s->n;
+        }
+    }
+    if ((rc = ensure_dirs(c, lmax + 1, st)) != ARC_OK) return rc;
+
+    HIP_TRY(c, hipEventRecord(c->ev[0], st));
+    HIP_TRY(c, launch_zero_u64(c->counters, kNumCounters, st));
+    HIP_TRY(c, launch_zero_f64(c->acc, 8, st));
+    HIP_TRY(c, hipMemsetAsync(c->errflag, 0, sizeof(int), st));
+
+    OpacityArgs oa{};
+    oa.nb = nb;
+    oa.ncell = (uint32_t)ncell;
+    oa.L = g->cell_cm;
+    oa.y = g->y_he;
+    for (int k = 0; k < nb; ++k)
+        for (int sp = 0; sp < 3; ++sp) oa.sigma[k][sp] = b->sigma[3 * k + sp];
+    oa.n_h = g->n_h;
+    oa.x_hi = g->x_hi;
+    oa.x_hei = g->x_hei;
+    oa.x_heii = g->x_heii;
+    oa.kappa1 = nb == 1 ? (float*)c->kappa : nullptr;
+    oa.kappa4 = nb == 1 ? nullptr : (float4*)c->kappa;
+    oa.J = c->J;
+    oa.nbp = nbp;
+    oa.errflag = c->errflag;
+    HIP_TRY(c, launch_opacity(oa, st));
+
+    if (s->n > 0) {
+        HIP_TRY(c, hipMemcpyAsync(c->src_pos, s->pos, s->n * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(c->src_ndot, s->ndot, s->n * sizeof(double), hipMemcpyHostToDevice, st));
+        double f[kMaxBins];
+        for (int k = 0; k < nb; ++k) f[k] = b->frac[k] / (12.0 * uj[k]);
+        HIP_TRY(c, launch_sources(s->n, c->src_pos, c->src_ndot, f, nb, c->src, st));
+    }
+
+    TraceArgs A{};
+    A.nx = g->nx;
+    A.ny = g->ny;
+    A.nz = g->nz;
+    A.nb = nb;
+    A.level0 = p->level0;
+    A.lmax = lmax;
+    const float base = split_base(p->rays_per_cell);
+    for (int l = 0; l < kMaxLevels; ++l) A.tsplit[l] = l < lmax ? std::ldexp(base, l) : INFINITY;
+    A.tau_term = p->eps_term > 0 ? (float)(-std::log(p->eps_term)) : INFINITY;
+    A.kappa1 = oa.kappa1;
+    A.kappa4 = oa.kappa4;
+    A.J = c->J;
+    A.nbp = nbp;
+    A.src = c->src;
+    A.dirs = c->dirs;
+    for (int l = 0; l < kMaxLevels; ++l) A.dir_off[l] = l < c->dirs_levels ? c->dir_off[l] : 0;
+    A.esc = c->acc;
+    A.counters = c->counters;
+    A.tree = (unsigned long long*)p->tree_out;
+    A.tree_cap = p->tree_out ? p->tree_cap : 0;
+
+    HIP_TRY(c, hipEventRecord(c->ev[1], st));
+    const uint32_t npix0 = 12u << (2 * p->level0);
+    if (s->n > 0 && p->schedule == ARC_SCHED_PLAIN) {
+        // Section 2.1 iii: one source at a time, one HEALPix level per launch; the host
+        // reads back the number of children before launching the next level.
+        for (int si = 0; si < s->n; ++si) {
+            size_t n = npix0;
+            if (4 * n > c->rays_cap) {
+                size_t cap_bytes = c->rays_cap * sizeof(RayRec);
+                size_t cap2 = cap_bytes;
+                HIP_TRY(c, grow(&c->rays[0], &cap_bytes, 4 * n * sizeof(RayRec)));
+                HIP_TRY(c, grow(&c->rays[1], &cap2, 4 * n * sizeof(RayRec)));
+                c->rays_cap = 4 * n;
+            }
+            HIP_TRY(c, launch_seed_roots((uint32_t)si, 1, p->level0, c->rays[0], st));
+            int cur = 0;
+            while (n > 0) {
+                const size_t need = 4 * n;
+                if (need > c->rays_cap) {
+                    // grow both arrays, keeping the current level's rays
+                    RayRec* a = nullptr;
+                    RayRec* bb = nullptr;
+                    HIP_TRY(c, hipStreamSynchronize(st));
+                    HIP_TRY(c, hipMalloc((void**)&a, need * sizeof(RayRec)));
+                    HIP_TRY(c, hipMalloc((void**)&bb, need * sizeof(RayRec)));
+                    HIP_TRY(c, hipMemcpyAsync(a, c->rays[cur], n * sizeof(RayRec), hipMemcpyDeviceToDevice, st));
+                    HIP_TRY(c, hipStreamSynchronize(st));
+                    HIP_TRY(c, hipFree(c->rays[0]));
+                    HIP_TRY(c, hipFree(c->rays[1]));
+                    c->rays[0] = a;
+                    c->rays[1] = bb;
+                    cur = 0;
+                    c->rays_cap = need;
+                }
+                HIP_TRY(c, hipMemsetAsync(c->u32, 0, sizeof(uint32_t), st));
+                HIP_TRY(c, launch_trace_rays(A, p->precision, c->rays[cur], nullptr, (uint32_t)n, c->rays[1 - cur],
+                                             c->u32, (uint32_t)c->rays_cap, st));
+                uint32_t nn = 0;
+                HIP_TRY(c, hipMemcpyAsync(&nn, c->u32, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+                HIP_TRY(c, hipStreamSynchronize(st));
+                n = nn;
+                cur = 1 - cur;
+            }
+        }
+    } else if (s->n > 0) {
+        // Levels level0 .. item_level-1 are traced level by level for every source at once
+        // (the ray count stays on the device); the rays of item_level are then the work
+        // items of one persistent launch that traces each subtree depth first.
+        int waves = p->tune_waves > 0 ? p->tune_waves : 4;
+        if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
+            return fail(c, ARC_E_ARG, "tune_waves must be 1, 2, 4 or 8");
+        const int blocks = p->tune_blocks > 0 ? p->tune_blocks : c->cus * (16 / waves);
+        const int refill = p->tune_refill > 0 ? std::min(64, p->tune_refill) : 8;
+        const double n_roots = (double)s->n * npix0;
+        int litem = p->level0;
+        if (p->tune_item_level > 0) {
+            litem = std::max(p->level0, std::min(lmax, (int)p->tune_item_level));
+        } else {
+            const double want = 16.0 * blocks * waves;
+            while (litem < lmax && n_roots * std::ldexp(1.0, 2 * (litem - p->level0)) < want &&
+                   n_roots * std::ldexp(1.0, 2 * (litem + 1 - p->level0)) <= (double)(1u << 26))
+                ++litem;
+        }
+        const double max_items = n_roots * std::ldexp(1.0, 2 * (litem - p->level0));
+        if (max_items > (double)0xFFFFFFF0u) return fail(c, ARC_E_UNSUPPORTED, "too many work items");
+        const size_t cap = (size_t)max_items;
+        if (cap > c->rays_cap) {
+            size_t cap_bytes = c->rays_cap * sizeof(RayRec);
+            size_t cap2 = cap_bytes;
+            HIP_TRY(c, grow(&c->rays[0], &cap_bytes, cap * sizeof(RayRec)));
+            HIP_TRY(c, grow(&c->rays[1], &cap2, cap * sizeof(RayRec)));
+            c->rays_cap = cap;
+        }
+        const uint32_t spill_cap = 4096;
+        const size_t spill_need = (size_t)blocks * waves * spill_cap;
+        if (spill_need > c->spill_entries) {
+            size_t cap_bytes = c->spill_entries * sizeof(RayRec);
+            HIP_TRY(c, grow(&c->spill, &cap_bytes, spill_need * sizeof(RayRec)));
+            c->spill_entries = spill_need;
+        }
+        HIP_TRY(c, launch_seed_roots(0, (uint32_t)s->n, p->level0, c->rays[0], st));
+        int cur = 0;
+        uint32_t* cnt = c->u32 + 2;  // [2], [3]: ray counts of consecutive levels
+        HIP_TRY(c, launch_set_u32(cnt, (uint32_t)n_roots, st));
+        size_t bound = (size_t)n_roots;
+        for (int l = p->level0; l < litem; ++l) {
+            uint32_t* cin = cnt + ((l - p->level0) & 1);
+            uint32_t* cout = cnt + ((l - p->level0 + 1) & 1);
+            HIP_TRY(c, launch_set_u32(cout, 0u, st));
+            HIP_TRY(c, launch_trace_rays(A, p->precision, c->rays[cur], cin, (uint32_t)bound, c->rays[1 - cur], cout,
+                                         (uint32_t)cap, st));
+            bound *= 4;
+            cur = 1 - cur;
+        }
+        HIP_TRY(c, launch_set_u32(c->u32 + 1, 0u, st));
+        HIP_TRY(c, launch_trace_persistent(A, p->precision, c->rays[cur], cnt + ((litem - p->level0) & 1), c->u32 + 1,
+                                           c->spill, spill_cap, blocks, waves, refill, st));
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[2], st));
+
+    FinalizeArgs fa{};
+    fa.nb = nb;
+    fa.nbp = nbp;
+    fa.ncell = (uint32_t)ncell;
+    const double L2 = g->cell_cm * g->cell_cm;
+    for (int k = 0; k < nb; ++k) {
+        fa.uj[k] = uj[k];
+        for (int sp = 0; sp < 3; ++sp) {
+            fa.gam[k][sp] = uj[k] * b->sigma[3 * k + sp] / L2;
+            const double excess = b->e_erg[k] - b->e_thr[sp];
+            fa.hea[k][sp] = excess > 0 ? uj[k] * b->sigma[3 * k + sp] * excess / L2 : 0.0;
+        }
+    }
+    fa.J = c->J;
+    fa.kappa1 = oa.kappa1;
+    fa.kappa4 = oa.kappa4;
+    fa.gamma = out->gamma;
+    fa.heat = out->heat;
+    fa.absorbed = c->acc + 4;
+    HIP_TRY(c, launch_finalize(fa, st));
+    HIP_TRY(c, hipEventRecord(c->ev[3], st));
+
+    unsigned long long cnt[kNumCounters];
+    double acc[8];
+    int errflag = 0;
+    HIP_TRY(c, hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(acc, c->acc, sizeof acc, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(&errflag, c->errflag, sizeof errflag, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+
+    c->last_nb = nb;
+    c->last_nbp = nbp;
+    c->last_ncell = ncell;
+    c->have_field = true;
+    if (errflag) return fail(c, ARC_E_RANGE, "grid values out of range (n_h <= 0, fraction outside [0,1] or non-finite)");
+    if (cnt[kQueueOverflow]) return fail(c, ARC_E_QUEUE, "ray queue capacity exceeded (%llu rays dropped)", cnt[kQueueOverflow]);
+    if (ledger) {
+        std::memset(ledger, 0, sizeof *ledger);
+        ledger->emitted = sum_ndot * dt;
+        double esc = 0;
+        for (int k = 0; k < nb; ++k) esc += acc[k] * uj[k];
+        ledger->escaped = esc * dt;
+        ledger->absorbed = acc[4] * dt;
+        ledger->crossings = cnt[kCrossings];
+        ledger->rays = cnt[kRays];
+        ledger->splits = cnt[kSplits];
+        ledger->terminated = cnt[kTerminated];
+        ledger->escaped_rays = cnt[kEscapedRays];
+        ledger->spills = cnt[kSpills];
+        ledger->tree_count = (int64_t)cnt[kTreeCount];
+        for (int k = 0; k < kMaxBins; ++k) ledger->u_j[k] = k < nb ? uj[k] : 0.0;
+        float ms = 0;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+        ledger->ms_trace = ms;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
+        ledger->ms_total = ms;
+    }
+    return ARC_OK;
+}
+
+arc_status arc_get_field(arc_ctx* c, int64_t* dst, int64_t count, void* stream)
+{
+    if (!c || !dst) return ARC_E_ARG;
+    if (!c->have_field) return fail(c, ARC_E_ARG, "no field: call arc_trace first");
+    if (count < (int64_t)(c->last_ncell * c->last_nb)) return fail(c, ARC_E_ARG, "dst too small");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, launch_get_field(c->J, c->last_nb, c->last_nbp, (uint32_t)c->last_ncell, (long long*)dst, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    return ARC_OK;
+}
+
+arc_status arc_healpix_dirs(arc_ctx* c, int32_t level, float* dst, void* stream)
+{
+    if (!c || !dst) return ARC_E_ARG;
+    if (level < 0 || level > 12) return fail(c, ARC_E_ARG, "level must be 0..12");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    arc_status rc = ensure_dirs(c, level + 1, st);
+    if (rc != ARC_OK) return rc;
+    const size_t npix = (size_t)12 << (2 * level);
+    // float4 table -> x, y, z triples
+    std::vector<float4> h(npix);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), c->dirs + c->dir_off[level], npix * sizeof(float4), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    std::vector<float> f(3 * npix);
+    for (size_t i = 0; i < npix; ++i) {
+        f[3 * i] = h[i].x;
+        f[3 * i + 1] = h[i].y;
+        f[3 * i + 2] = h[i].z;
+    }
+    HIP_TRY(c, hipMemcpyAsync(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    return ARC_OK;
+}
+
+arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, double dt, const arc_chem_params* p,
+                         arc_chem_stats* stats)
+{
+    if (!c) return ARC_E_ARG;
+    c->err.clear();
+    arc_status rc;
+    if ((rc = check_grid(c, g)) != ARC_OK) return rc;
+    if (!g->temp) return fail(c, ARC_E_ARG, "null temperature");
+    if (!r || !r->gamma || !r->heat) return fail(c, ARC_E_ARG, "null rates");
+    if (!p) return fail(c, ARC_E_ARG, "null params");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, ARC_E_RANGE, "dt must be finite and > 0");
+    if (!(p->eps > 0) || !std::isfinite(p->eps)) return fail(c, ARC_E_RANGE, "eps must be > 0");
+    if (p->max_sub < 1) return fail(c, ARC_E_RANGE, "max_sub must be >= 1");
+    if (p->rates != 0 && p->rates != 1) return fail(c, ARC_E_ARG, "rates must be 0 or 1");
+    if (p->rates == 0 && !(p->alpha_hii >= 0)) return fail(c, ARC_E_RANGE, "alpha_hii must be >= 0");
+    if (!(p->t_floor > 0)) return fail(c, ARC_E_RANGE, "t_floor must be > 0");
+    if (p->mode != ARC_CHEM_PLAIN) return fail(c, ARC_E_UNSUPPORTED, "chemistry mode %d not available", p->mode);
+    hipStream_t st = (hipStream_t)p->stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    ChemArgs a{};
+    a.ncell = (uint32_t)((size_t)g->nx * g->ny * g->nz);
+    a.y = g->y_he;
+    a.n_h = g->n_h;
+    a.x_hi = g->x_hi;
+    a.x_hei = g->x_hei;
+    a.x_heii = g->x_heii;
+    a.temp = g->temp;
+    a.gamma = r->gamma;
+    a.heat = r->heat;
+    a.dt = dt;
+    a.isothermal = p->isothermal;
+    a.rates = p->rates;
+    a.collisional = p->collisional;
+    a.max_sub = p->max_sub;
+    a.alpha_hii = p->alpha_hii;
+    a.eps = p->eps;
+    a.t_floor = p->t_floor;
+    a.stats = c->chem_stats;
+    HIP_TRY(c, launch_zero_u64(c->chem_stats, 4, st));
+    HIP_TRY(c, hipEventRecord(c->ev[0], st));
+    HIP_TRY(c, launch_chem(a, st));
+    HIP_TRY(c, hipEventRecord(c->ev[1], st));
+    unsigned long long cs[4];
+    HIP_TRY(c, hipMemcpyAsync(cs, c->chem_stats, sizeof cs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (stats) {
+        stats->cells = a.ncell;
+        stats->sub_total = (int64_t)cs[0];
+        stats->capped = (int64_t)cs[1];
+        stats->sub_max = (int32_t)cs[2];
+        float ms = 0;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        stats->ms = ms;
+    }
+    return ARC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// arc_kernels.h -- launch wrappers of libarc's kernels (host-callable).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "arc_device.h"
+
+namespace arc {
+
+struct OpacityArgs {
+    int nb;
+    uint32_t ncell;
+    double L, y;
+    double sigma[kMaxBins][3];
+    const float *n_h, *x_hi, *x_hei, *x_heii;
+    float* kappa1;
+    float4* kappa4;
+    unsigned long long* J;
+    int nbp;
+    int* errflag;
+};
+
+struct FinalizeArgs {
+    int nb, nbp;
+    uint32_t ncell;
+    double gam[kMaxBins][3];   // u_J,b sigma_bS / L^2
+    double hea[kMaxBins][3];   // u_J,b sigma_bS (E_b - E_S)^+ / L^2
+    double uj[kMaxBins];
+    const unsigned long long* J;
+    const float* kappa1;
+    const float4* kappa4;
+    float *gamma, *heat;       // [3][ncell]
+    double* absorbed;          // sum_c sum_b u_J J kappa
+};
+
+struct ChemArgs {
+    uint32_t ncell;
+    double y;
+    const float* n_h;
+    float *x_hi, *x_hei, *x_heii, *temp;
+    const float *gamma, *heat;
+    double dt;
+    int isothermal, rates, collisional, max_sub;
+    double alpha_hii, eps, t_floor;
+    unsigned long long* stats;  // [0] sub total, [1] capped, [2] max
+};
+
+hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
+hipError_t launch_opacity(const OpacityArgs& a, hipStream_t s);
+hipError_t launch_healpix(int level, float4* out, hipStream_t s);
+hipError_t launch_sources(int n, const double* pos, const double* ndot, const double* frac_over_12uj, int nb,
+                          SourceRec* out, hipStream_t s);
+hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, RayRec* out, hipStream_t s);
+// n_in_dev (optional) holds the ray count on the device; n_in bounds it and sizes the grid.
+hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, const uint32_t* n_in_dev, uint32_t n_in,
+                             RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s);
+hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
+                                   uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
+                                   int refill, hipStream_t s);
+int persistent_max_waves();
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, uint32_t ncell, long long* dst,
+                            hipStream_t s);
+hipError_t launch_chem(const ChemArgs& a, hipStream_t s);
+
+}  // namespace arc

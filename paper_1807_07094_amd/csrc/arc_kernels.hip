@@ -1,0 +1,704 @@
+// arc_kernels.hip -- gfx950 kernels of libarc.
+//
+//   k_opacity          optical depth per cell length for every bin, field zeroing, input checks
+//   k_healpix          FP32 HEALPix pixel centres of one level (computed in FP64)
+//   k_sources          per-source table (lattice position, root-ray photon rate)
+//   k_seed_roots       root rays of a range of sources
+//   k_trace_rays       one ray per lane, rays of one HEALPix level (the per-level schedule)
+//   k_trace_persistent every source in one launch: device work queue, wave-ballot refill,
+//                      per-wave LDS ray stack with a private spill area in memory
+//   k_finalize         fixed-point field -> photoionisation and photoheating rates
+//   k_get_field        field copy in [bin][cell] order
+//   k_chem             sub-cycled backward-difference chemistry and energy update
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "arc_kernels.h"
+
+namespace arc {
+
+namespace {
+
+inline unsigned grid_for(size_t n, unsigned block, unsigned cap = 65536u)
+{
+    size_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------------------------
+// Small utilities.
+// -------------------------------------------------------------------------------------
+__global__ void k_zero_u64(unsigned long long* p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+__global__ void k_zero_f64(double* p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s)
+{
+    k_zero_u64<<<grid_for(n, 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s)
+{
+    k_set_u32<<<1, 1, 0, s>>>(p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s)
+{
+    k_zero_f64<<<grid_for(n, 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------------------
+// Opacity (section 2.2: tau per bin summed over HI, HeI, HeII) and field zeroing
+// (section 2.1 step i). One pass over the grid; invalid inputs raise a flag.
+// -------------------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256) void k_opacity(OpacityArgs a)
+{
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
+        const float n = a.n_h[c], xh = a.x_hi[c], x1 = a.x_hei[c], x2 = a.x_heii[c];
+        const bool ok = isfinite(n) && n > 0.0f && xh >= 0.0f && xh <= 1.0f && x1 >= 0.0f && x1 <= 1.0f &&
+                        x2 >= 0.0f && x2 <= 1.0f;
+        if (!ok) atomicOr(a.errflag, 1);
+        float k[kMaxBins] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            k[b] = (float)(a.L * (double)n *
+                           (a.sigma[b][0] * (double)xh + a.y * (a.sigma[b][1] * (double)x1 + a.sigma[b][2] * (double)x2)));
+        if constexpr (NB == 1) {
+            a.kappa1[c] = k[0];
+            a.J[c] = 0ull;
+        } else {
+            a.kappa4[c] = make_float4(k[0], k[1], k[2], k[3]);
+            unsigned long long* j = a.J + (size_t)c * a.nbp;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b < a.nbp) j[b] = 0ull;
+        }
+    }
+}
+
+hipError_t launch_opacity(const OpacityArgs& a, hipStream_t s)
+{
+    const unsigned g = grid_for(a.ncell, 256, 1u << 20);
+    switch (a.nb) {
+        case 1: k_opacity<1><<<g, 256, 0, s>>>(a); break;
+        case 2: k_opacity<2><<<g, 256, 0, s>>>(a); break;
+        case 3: k_opacity<3><<<g, 256, 0, s>>>(a); break;
+        default: k_opacity<4><<<g, 256, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------------------
+// HEALPix pixel centres, nested scheme (Gorski et al. 2005). The base faces form three
+// rows of four; inside a face the nested index interleaves the bits of the face
+// coordinates (x even, y odd). The ring index and the position inside the ring give
+// z exactly as a ratio of integers and phi as an exact multiple of pi/2.
+// -------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t compact_bits(uint64_t v)
+{
+    v &= 0x5555555555555555ull;
+    v = (v | (v >> 1)) & 0x3333333333333333ull;
+    v = (v | (v >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    v = (v | (v >> 4)) & 0x00FF00FF00FF00FFull;
+    v = (v | (v >> 8)) & 0x0000FFFF0000FFFFull;
+    v = (v | (v >> 16)) & 0x00000000FFFFFFFFull;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_healpix(int level, float4* out)
+{
+    const long long ns = 1ll << level;
+    const long long per_face = ns * ns;
+    const long long npix = 12 * per_face;
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < npix;
+         p += (long long)gridDim.x * blockDim.x) {
+        const int face = (int)(p / per_face);
+        const uint64_t q = (uint64_t)(p - face * per_face);
+        const long long fx = (long long)compact_bits(q), fy = (long long)compact_bits(q >> 1);
+        const int row = face >> 2, col = face & 3;
+        // the face's lowest corner sits on ring (row + 2) Nside
+        const long long ring = (row + 2) * ns - fx - fy - 1;
+        long long nr, num_z, den_z;
+        int shift;
+        if (ring < ns) {
+            nr = ring;
+            shift = 0;
+            num_z = 3 * ns * ns - nr * nr;
+            den_z = 3 * ns * ns;
+        } else if (ring > 3 * ns) {
+            nr = 4 * ns - ring;
+            shift = 0;
+            num_z = -(3 * ns * ns - nr * nr);
+            den_z = 3 * ns * ns;
+        } else {
+            nr = ns;
+            shift = (int)((ring - ns) & 1);
+            num_z = 2 * (2 * ns - ring);
+            den_z = 3 * ns;
+        }
+        const double z = (double)num_z / (double)den_z;
+        // longitude index of the face corner, in units of pi/4: odd in the polar rows
+        const long long lon0 = 2 * col + (row == 1 ? 0 : 1);
+        long long j = (lon0 * nr + fx - fy + 1 + shift) / 2;
+        if (j > 4 * nr) j -= 4 * nr;
+        if (j < 1) j += 4 * nr;
+        // phi / (pi/2) = (2j - 1 - shift) / (2 nr)
+        const long long num = 2 * j - 1 - shift, den = 2 * nr;
+        const long long quad = num / den, rem = num - quad * den;
+        double sa, ca;
+        sincospi(0.5 * ((double)rem / (double)den), &sa, &ca);
+        double cx, cy;
+        if (quad == 0) {
+            cx = ca;
+            cy = sa;
+        } else if (quad == 1) {
+            cx = -sa;
+            cy = ca;
+        } else if (quad == 2) {
+            cx = -ca;
+            cy = -sa;
+        } else {
+            cx = sa;
+            cy = -ca;
+        }
+        const double st = sqrt((1.0 - z) * (1.0 + z));
+        out[p] = make_float4((float)(st * cx), (float)(st * cy), (float)z, 0.0f);
+    }
+}
+
+hipError_t launch_healpix(int level, float4* out, hipStream_t s)
+{
+    const long long npix = 12ll << (2 * level);
+    k_healpix<<<grid_for((size_t)npix, 256, 1u << 20), 256, 0, s>>>(level, out);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------------------
+// Source table and root rays (section 2.1 iii a: rays start at radius 0 with zero
+// optical depth; section 2.4: each ray carries an equal share of the source's photons).
+// -------------------------------------------------------------------------------------
+struct ScaleArg {
+    double f[kMaxBins];
+};
+
+__global__ void k_sources(int n, const double* pos, const double* ndot, ScaleArg sc, int nb, SourceRec* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    SourceRec r;
+    r.x = (float)pos[3 * i];
+    r.y = (float)pos[3 * i + 1];
+    r.z = (float)pos[3 * i + 2];
+    r.pad = 0.0f;
+#pragma unroll
+    for (int b = 0; b < kMaxBins; ++b) r.scale[b] = b < nb ? (float)(ndot[i] * sc.f[b]) : 0.0f;
+    out[i] = r;
+}
+
+hipError_t launch_sources(int n, const double* pos, const double* ndot, const double* frac_over_12uj, int nb,
+                          SourceRec* out, hipStream_t s)
+{
+    ScaleArg sc;
+    for (int b = 0; b < kMaxBins; ++b) sc.f[b] = b < nb ? frac_over_12uj[b] : 0.0;
+    if (n > 0) k_sources<<<grid_for(n, 256), 256, 0, s>>>(n, pos, ndot, sc, nb, out);
+    return hipGetLastError();
+}
+
+__global__ void k_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, RayRec* out)
+{
+    const uint32_t npix = 12u << (2 * level0);
+    const size_t n = (size_t)nsrc * npix;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        RayRec r;
+        r.src = first_src + (uint32_t)(i / npix);
+        r.lp = ((uint32_t)level0 << kLevelShift) | (uint32_t)(i % npix);
+        r.pad0 = r.pad1 = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) r.tau[b] = r.taulo[b] = 0.0f;
+        out[i] = r;
+    }
+}
+
+hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, RayRec* out, hipStream_t s)
+{
+    const size_t n = (size_t)nsrc * (12u << (2 * level0));
+    k_seed_roots<<<grid_for(n, 256), 256, 0, s>>>(first_src, nsrc, level0, out);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------------------
+// Per-level schedule (section 2.1 iii b/c): one ray per lane, traced until it splits,
+// terminates or leaves the grid; splitting lanes write their four children into the
+// next level's array, one slot reservation per wave.
+// -------------------------------------------------------------------------------------
+template <int NB, int PREC>
+__global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* __restrict__ in,
+                                                    const uint32_t* n_in_dev, uint32_t n_in_host,
+                                                    RayRec* __restrict__ out, uint32_t* n_out, uint32_t out_cap)
+{
+    const uint32_t n_in = n_in_dev ? *n_in_dev : n_in_host;
+    LaneStats st;
+    st.clear();
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = __lanemask_lt();
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n_in; base += stride) {
+        const uint32_t i = base + threadIdx.x;
+        int ev = kEscape;
+        Ray<NB> ray;
+        if (i < n_in) {
+            const RayRec r = in[i];
+            record_tree<NB>(A, r.src, r.lp);
+            if (ray_init<NB>(A, r, ray, st)) {
+                do {
+                    ev = ray_step<NB, PREC>(A, ray, st);
+                } while (ev == kContinue);
+            } else {
+                ev = kEscape;
+            }
+        }
+        const uint64_t m = __ballot(ev == kSplit);
+        if (m) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t wbase = 0;
+            if (lane == leader) wbase = atomicAdd(n_out, 4u * (uint32_t)__popcll(m));
+            wbase = __shfl(wbase, leader, 64);
+            if (ev == kSplit) {
+                const uint32_t slot = wbase + 4u * (uint32_t)__popcll(m & lt);
+                if (slot + 4u <= out_cap) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) out[slot + k] = child_rec<NB>(ray, k);
+                } else {
+                    atomicAdd(&A.counters[kQueueOverflow], 1ull);
+                }
+            }
+        }
+    }
+    flush_stats<NB>(A, st);
+}
+
+template <int NB>
+static hipError_t trace_rays_nb(const TraceArgs& A, int prec, const RayRec* in, const uint32_t* n_in_dev,
+                                uint32_t n_in, RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s)
+{
+    const unsigned g = grid_for(n_in, 256, 1u << 16);
+    if (prec == 0)
+        k_trace_rays<NB, 0><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+    else
+        k_trace_rays<NB, 1><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, const uint32_t* n_in_dev, uint32_t n_in,
+                             RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s)
+{
+    switch (A.nb) {
+        case 1: return trace_rays_nb<1>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, s);
+        case 2: return trace_rays_nb<2>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, s);
+        case 3: return trace_rays_nb<3>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, s);
+        default: return trace_rays_nb<4>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, s);
+    }
+}
+
+// -------------------------------------------------------------------------------------
+// Batched schedule: after the first levels have been traced level by level (so that there
+// are enough independent subtrees), one persistent launch traces every remaining subtree.
+//
+// Each wave keeps 64 rays in flight, one per lane, and advances them one crossing per
+// iteration. Lanes whose ray ends are refilled (once at least `refill` lanes are idle)
+// from the wave's LDS stack, then from the wave's private spill area, then from the
+// global work queue of subtree roots (one atomic per refill). A splitting lane continues
+// with child 0 and pushes children 1-3. The LDS stack is a ring: when it would overflow,
+// its oldest entries move to the top of the spill area, so the pair behaves as one LIFO
+// stack and the wave works depth first. Waves share nothing but the work-queue head, so
+// each wave ends when the queue is drained and its own stacks are empty.
+// -------------------------------------------------------------------------------------
+constexpr int kStackCap = 256;  // power of two, >= 3 * 64 children of one split round
+
+template <int NB, int PREC, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
+                                                               const uint32_t* n_items_dev, uint32_t* head,
+                                                               RayRec* __restrict__ spill_all, uint32_t spill_cap,
+                                                               int refill)
+{
+    __shared__ RayRec lds[WPB * kStackCap];
+    const int wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = __lanemask_lt();
+    const uint32_t n_items = *n_items_dev;
+    RayRec* stk = lds + wid * kStackCap;
+    RayRec* spill = spill_all + (size_t)(blockIdx.x * WPB + wid) * spill_cap;
+    int base = 0;          // ring start (oldest entry), wave-uniform
+    int top = 0;           // entries in the ring, wave-uniform
+    uint32_t nspill = 0;   // wave-uniform
+    bool qdone = false;    // wave-uniform
+    uint32_t spilled = 0;
+    bool has = false;
+    Ray<NB> ray;
+    LaneStats st;
+    st.clear();
+    for (;;) {
+        const uint64_t idle = __ballot(!has);
+        const int nidle = __popcll(idle);
+        const bool pending = top > 0 || nspill > 0 || !qdone;
+        if (nidle > 0 && pending && (nidle >= refill || nidle == 64)) {
+            const int rank = __popcll(idle & lt);
+            RayRec r;
+            bool got = false;
+            int take = min(nidle, top);
+            if (!has && rank < take) {
+                r = stk[(base + top - 1 - rank) & (kStackCap - 1)];
+                got = true;
+            }
+            top -= take;
+            int rem = nidle - take;
+            if (rem > 0 && nspill > 0) {
+                const int t2 = min(rem, (int)nspill);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (!has && rank >= take && rank < take + t2) {
+                    r = spill[nspill - 1u - (uint32_t)(rank - take)];
+                    got = true;
+                }
+                nspill -= (uint32_t)t2;
+                take += t2;
+                rem -= t2;
+            }
+            if (rem > 0 && !qdone) {
+                uint32_t b0 = 0;
+                if (lane == 0) b0 = atomicAdd(head, (uint32_t)rem);
+                b0 = __shfl(b0, 0, 64);
+                if (b0 >= n_items) {
+                    qdone = true;
+                } else {
+                    const uint32_t avail = min((uint32_t)rem, n_items - b0);
+                    if (!has && rank >= take && rank < take + (int)avail) {
+                        r = items[b0 + (uint32_t)(rank - take)];
+                        got = true;
+                    }
+                    if (b0 + (uint32_t)rem >= n_items) qdone = true;
+                }
+            }
+            if (got) {
+                record_tree<NB>(A, r.src, r.lp);
+                has = ray_init<NB>(A, r, ray, st);
+            }
+        }
+        if (!__any(has)) {
+            if (top == 0 && nspill == 0 && qdone) break;
+            continue;
+        }
+        int ev = kContinue;
+        if (has) ev = ray_step<NB, PREC>(A, ray, st);
+        const uint64_t sp = __ballot(ev == kSplit);
+        if (sp) {
+            const int need = 3 * __popcll(sp);
+            if (top + need > kStackCap) {
+                // move the oldest entries to the top of the spill area
+                const int m = top + need - kStackCap;
+                for (int i = lane; i < m; i += 64) {
+                    const uint32_t g = nspill + (uint32_t)i;
+                    if (g < spill_cap)
+                        spill[g] = stk[(base + i) & (kStackCap - 1)];
+                    else
+                        atomicAdd(&A.counters[kQueueOverflow], 1ull);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                spilled += (uint32_t)m;
+                nspill = min(spill_cap, nspill + (uint32_t)m);
+                base = (base + m) & (kStackCap - 1);
+                top -= m;
+            }
+            if (ev == kSplit) {
+                const int srank = __popcll(sp & lt);
+#pragma unroll
+                for (int k = 1; k < 4; ++k)
+                    stk[(base + top + 3 * srank + (k - 1)) & (kStackCap - 1)] = child_rec<NB>(ray, k);
+            }
+            top += need;
+            if (ev == kSplit) {
+                const RayRec c0 = child_rec<NB>(ray, 0);
+                record_tree<NB>(A, c0.src, c0.lp);
+                has = ray_init<NB>(A, c0, ray, st);
+            }
+        }
+        if (ev == kTerminate || ev == kEscape) has = false;
+    }
+    flush_stats<NB>(A, st);
+    if (lane == 0 && spilled) atomicAdd(&A.counters[kSpills], (unsigned long long)spilled);
+}
+
+constexpr int kMaxWavesPerBlock = 8;
+
+int persistent_max_waves() { return kMaxWavesPerBlock; }
+
+template <int NB, int PREC>
+static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const uint32_t* n_items, uint32_t* head,
+                                RayRec* spill, uint32_t spill_cap, int blocks, int waves, int refill, hipStream_t s)
+{
+    switch (waves) {
+        case 1: k_trace_persistent<NB, PREC, 1><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 2: k_trace_persistent<NB, PREC, 2><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 4: k_trace_persistent<NB, PREC, 4><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        default: k_trace_persistent<NB, PREC, 8><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
+                                   uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
+                                   int refill, hipStream_t s)
+{
+#define ARC_PERSIST(NBV)                                                                                     \
+    return prec == 0 ? persistent_nb<NBV, 0>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s) \
+                     : persistent_nb<NBV, 1>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s)
+    switch (A.nb) {
+        case 1: ARC_PERSIST(1);
+        case 2: ARC_PERSIST(2);
+        case 3: ARC_PERSIST(3);
+        default: ARC_PERSIST(4);
+    }
+#undef ARC_PERSIST
+}
+
+// -------------------------------------------------------------------------------------
+// Rates from the fixed-point field (eq:ion per absorber with the in-bin species split,
+// section 2.8 heating) and the absorbed-photon ledger.
+// -------------------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a)
+{
+    double absorbed = 0.0;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
+        double Jb[NB];
+        const unsigned long long* j = a.J + (size_t)c * a.nbp;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Jb[b] = (double)(long long)j[b];
+        float k[NB];
+        if constexpr (NB == 1) {
+            k[0] = a.kappa1[c];
+        } else {
+            const float4 v = a.kappa4[c];
+            k[0] = v.x;
+            k[1] = v.y;
+            if constexpr (NB > 2) k[2] = v.z;
+            if constexpr (NB > 3) k[3] = v.w;
+        }
+#pragma unroll
+        for (int sp = 0; sp < 3; ++sp) {
+            double g = 0.0, h = 0.0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                g += a.gam[b][sp] * Jb[b];
+                h += a.hea[b][sp] * Jb[b];
+            }
+            a.gamma[(size_t)sp * a.ncell + c] = (float)g;
+            a.heat[(size_t)sp * a.ncell + c] = (float)h;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) absorbed += a.uj[b] * Jb[b] * (double)k[b];
+    }
+    absorbed = wave_sum_f64(absorbed);
+    if ((threadIdx.x & 63) == 0 && absorbed != 0.0) atomicAdd(a.absorbed, absorbed);
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s)
+{
+    const unsigned g = grid_for(a.ncell, 256, 1u << 16);
+    switch (a.nb) {
+        case 1: k_finalize<1><<<g, 256, 0, s>>>(a); break;
+        case 2: k_finalize<2><<<g, 256, 0, s>>>(a); break;
+        case 3: k_finalize<3><<<g, 256, 0, s>>>(a); break;
+        default: k_finalize<4><<<g, 256, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_get_field(const unsigned long long* J, int nb, int nbp, uint32_t ncell, long long* dst)
+{
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x)
+        for (int b = 0; b < nb; ++b) dst[(size_t)b * ncell + c] = (long long)J[(size_t)c * nbp + b];
+}
+
+hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, uint32_t ncell, long long* dst,
+                            hipStream_t s)
+{
+    k_get_field<<<grid_for(ncell, 256, 1u << 16), 256, 0, s>>>(J, nb, nbp, ncell, dst);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------------------
+// Chemistry (eq:diffeq in the backward-difference form of eq:anninos, sub-cycled with
+// the step limit of section 2.7; heating and cooling of section 2.8). One cell per
+// lane. Rate coefficients and cooling in FP32, species and energy in FP64.
+// Coefficients: Hui & Gnedin (1997) fits with lambda = 2 T_i / T.
+// -------------------------------------------------------------------------------------
+namespace chem {
+
+constexpr float kTHI = 157807.0f, kTHeI = 285335.0f, kTHeII = 631515.0f;
+constexpr double kKB = 1.380649e-16;
+constexpr double kEV = 1.602176634e-12;
+
+struct Coef {
+    float a_hii, a_heii, a_heiii, k_hi, k_hei, k_heii;
+};
+
+__device__ __forceinline__ Coef coefficients(float T)
+{
+    const float lhi = 2.0f * kTHI / T, lhei = 2.0f * kTHeI / T, lheii = 2.0f * kTHeII / T;
+    const float t15 = powf(T, -1.5f);
+    Coef c;
+    c.a_hii = 2.753e-14f * powf(lhi, 1.5f) / powf(1.0f + powf(lhi / 2.740f, 0.407f), 2.242f);
+    const float diel = 1.90e-3f * t15 * expf(-0.75f * lheii / 2.0f) * (1.0f + 0.3f * expf(-0.15f * lheii / 2.0f));
+    c.a_heii = 1.26e-14f * powf(lhei, 0.750f) + diel;
+    c.a_heiii = 2.0f * 2.753e-14f * powf(lheii, 1.5f) / powf(1.0f + powf(lheii / 2.740f, 0.407f), 2.242f);
+    c.k_hi = 21.11f * t15 * expf(-lhi / 2.0f) * powf(lhi, -1.089f) / powf(1.0f + powf(lhi / 0.354f, 0.874f), 1.101f);
+    c.k_hei = 32.38f * t15 * expf(-lhei / 2.0f) * powf(lhei, -1.146f) / powf(1.0f + powf(lhei / 0.416f, 0.987f), 1.056f);
+    c.k_heii = 19.95f * t15 * expf(-lheii / 2.0f) * powf(lheii, -1.089f) / powf(1.0f + powf(lheii / 0.553f, 0.735f), 1.275f);
+    return c;
+}
+
+// Cooling per volume [erg cm^-3 s^-1]: recombination, collisional ionisation,
+// collisional excitation, bremsstrahlung. Rate coefficients in FP32, products in FP64.
+__device__ __forceinline__ double cooling(float T, const Coef& k, double ne, double nhi, double nhii, double nhei,
+                                          double nheii, double nheiii, int collisional)
+{
+    const float lhi = 2.0f * kTHI / T, lhei = 2.0f * kTHeI / T, lheii = 2.0f * kTHeII / T;
+    const float rec_hii = 3.435e-30f * T * powf(lhi, 1.970f) / powf(1.0f + powf(lhi / 2.250f, 0.376f), 3.720f);
+    const float rec_heii = 1.380649e-16f * T * 1.26e-14f * powf(lhei, 0.750f);
+    const float rec_heiii = 8.0f * 3.435e-30f * T * powf(lheii, 1.970f) / powf(1.0f + powf(lheii / 2.250f, 0.376f), 3.720f);
+    const float diel = 1.90e-3f * powf(T, -1.5f) * expf(-0.75f * lheii / 2.0f) * (1.0f + 0.3f * expf(-0.15f * lheii / 2.0f));
+    const double diel_cool = 0.75 * 54.418 * kEV * (double)diel;
+    double lam = ne * ((double)rec_hii * nhii + (double)rec_heii * nheii + (double)rec_heiii * nheiii + diel_cool * nheii);
+    if (collisional)
+        lam += ne * (13.598 * kEV * (double)k.k_hi * nhi + 24.587 * kEV * (double)k.k_hei * nhei +
+                     54.418 * kEV * (double)k.k_heii * nheii);
+    const float damp = 1.0f + sqrtf(T / 1e5f);
+    lam += ne * nhi * (double)(7.5e-19f * expf(-0.75f * lhi / 2.0f) / damp);
+    lam += ne * nheii * (double)(5.54e-17f * powf(T, -0.397f) * expf(-0.75f * lheii / 2.0f) / damp);
+    const float lt = log10f(T);
+    const float gff = 1.1f + 0.34f * expf(-(5.5f - lt) * (5.5f - lt) / 3.0f);
+    lam += (double)(1.42e-27f * gff * sqrtf(T)) * (nhii + nheii + 4.0 * nheiii) * ne;
+    return lam;
+}
+
+}  // namespace chem
+
+__global__ __launch_bounds__(256) void k_chem(ChemArgs a)
+{
+    unsigned long long sub_total = 0, capped = 0;
+    unsigned int sub_max = 0;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
+        const double nh = a.n_h[c], nhe = a.y * nh;
+        double nhi = nh * (double)a.x_hi[c], nhii = nh - nhi;
+        double nhei = nhe * (double)a.x_hei[c], nheii = nhe * (double)a.x_heii[c];
+        double nheiii = nhe - nhei - nheii;
+        if (nheiii < 0) nheiii = 0;
+        float T = a.temp[c];
+        double ne = nhii + nheii + 2.0 * nheiii;
+        double E = 1.5 * chem::kKB * (double)T * (nh + nhe + ne);
+        const double ghi = a.gamma[c], ghei = a.gamma[(size_t)a.ncell + c], gheii = a.gamma[2 * (size_t)a.ncell + c];
+        const double hhi = a.heat[c], hhei = a.heat[(size_t)a.ncell + c], hheii = a.heat[2 * (size_t)a.ncell + c];
+        double t = 0.0;
+        int n = 0;
+        bool cap = false;
+        while (t < a.dt) {
+            chem::Coef k{};
+            if (a.rates == 0) {
+                k.a_hii = (float)a.alpha_hii;
+            } else {
+                k = chem::coefficients(T);
+                if (!a.collisional) k.k_hi = k.k_hei = k.k_heii = 0.0f;
+            }
+            const double ndot_hi = (double)k.a_hii * ne * nhii - (ghi + (double)k.k_hi * ne) * nhi;
+            double edot = 0.0;
+            if (!a.isothermal)
+                edot = nhi * hhi + nhei * hhei + nheii * hheii -
+                       chem::cooling(T, k, ne, nhi, nhii, nhei, nheii, nheiii, a.collisional);
+            double h = a.dt - t;
+            bool last = true;
+            if (n >= a.max_sub) {
+                cap = true;
+            } else {
+                if (edot != 0.0 && a.eps * E / fabs(edot) < h) {
+                    h = a.eps * E / fabs(edot);
+                    last = false;
+                }
+                if (nhi > 0.0 && ndot_hi != 0.0 && a.eps * nhi / fabs(ndot_hi) < h) {
+                    h = a.eps * nhi / fabs(ndot_hi);
+                    last = false;
+                }
+                if (nhii > 0.0 && ndot_hi != 0.0 && a.eps * nhii / fabs(ndot_hi) < h) {
+                    h = a.eps * nhii / fabs(ndot_hi);
+                    last = false;
+                }
+            }
+            nhi = (nhi + (double)k.a_hii * ne * nhii * h) / (1.0 + (ghi + (double)k.k_hi * ne) * h);
+            if (nhi > nh) nhi = nh;
+            nhii = nh - nhi;
+            double nhei_new = (nhei + (double)k.a_heii * ne * nheii * h) / (1.0 + (ghei + (double)k.k_hei * ne) * h);
+            double nheiii_new = (nheiii + (gheii + (double)k.k_heii * ne) * nheii * h) / (1.0 + (double)k.a_heiii * ne * h);
+            if (nhei_new > nhe) nhei_new = nhe;
+            if (nheiii_new > nhe - nhei_new) nheiii_new = nhe - nhei_new;
+            nhei = nhei_new;
+            nheiii = nheiii_new;
+            nheii = nhe - nhei - nheiii;
+            if (nheii < 0.0) nheii = 0.0;
+            ne = nhii + nheii + 2.0 * nheiii;
+            if (!a.isothermal) {
+                E += edot * h;
+                double Td = E / (1.5 * chem::kKB * (nh + nhe + ne));
+                if (Td < a.t_floor) {
+                    Td = a.t_floor;
+                    E = 1.5 * chem::kKB * Td * (nh + nhe + ne);
+                }
+                T = (float)Td;
+            }
+            t = last ? a.dt : t + h;
+            ++n;
+        }
+        a.x_hi[c] = (float)(nhi / nh);
+        if (nhe > 0.0) {
+            a.x_hei[c] = (float)(nhei / nhe);
+            a.x_heii[c] = (float)(nheii / nhe);
+        }
+        a.temp[c] = T;
+        sub_total += (unsigned long long)n;
+        capped += cap ? 1ull : 0ull;
+        sub_max = max(sub_max, (unsigned)n);
+    }
+    sub_total = wave_sum_u64(sub_total);
+    capped = wave_sum_u64(capped);
+    for (int off = 32; off > 0; off >>= 1) sub_max = max(sub_max, (unsigned)__shfl_xor((int)sub_max, off, 64));
+    if ((threadIdx.x & 63) == 0) {
+        if (sub_total) atomicAdd(&a.stats[0], sub_total);
+        if (capped) atomicAdd(&a.stats[1], capped);
+        atomicMax(&a.stats[2], (unsigned long long)sub_max);
+    }
+}
+
+hipError_t launch_chem(const ChemArgs& a, hipStream_t s)
+{
+    k_chem<<<grid_for(a.ncell, 256, 1u << 16), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace arc

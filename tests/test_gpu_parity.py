@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded
+inputs. Bars: HEALPix split trees and crossing counts bit-exact in geometry mode; per-cell
+rates within 1e-4 relative where above 1e-6 of the maximum; photon conservation 1e-6;
+plain and batched schedules bitwise equal; run-to-run bitwise equal."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import (CONSERVATION_TOL, FRACTION_TOL, GAMMA_REL_TOL, conservation, rate_errors, run_gpu_trace,
+                     run_oracle)
+from paper_1807_07094_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(arc):
+    c = arc.Context(0)
+    yield c
+    c.close()
+
+
+def small_lognormal(shape=(40, 48, 56), n_src=4, seed=21, **kw):
+    return W.lognormal(0, n_src, seed, source_cells="uniform", shape=shape, **kw)
+
+
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("level", [0, 1, 2, 3, 5, 8])
+def test_healpix_directions_match_oracle(arc, ctx, level):
+    import torch
+
+    n = 12 * 4 ** level
+    dst = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+    ctx.healpix_dirs(level, dst)
+    gpu = dst.cpu().numpy().reshape(n, 3)
+    ref = oracle.healpix_vec(level, np.arange(n)).astype(np.float32)
+    ulp = np.abs(gpu.view(np.int32).astype(np.int64) - ref.view(np.int32).astype(np.int64))
+    # identical except where the FP64 value sits within rounding of an FP32 midpoint
+    assert ulp.max() <= 1
+    assert (ulp > 0).sum() <= max(1, n // 10 ** 6)
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched"])
+def test_c1_parity(arc, ctx, schedule):
+    w = W.c1()
+    g = run_gpu_trace(arc, ctx, w, schedule=schedule, tree_cap=1 << 20)
+    o = run_oracle(w, tree_cap=1 << 20)
+    errs = rate_errors(g, o)
+    assert errs[0] <= GAMMA_REL_TOL, errs
+    assert conservation(g["ledger"]) <= CONSERVATION_TOL
+    assert g["ledger"]["crossings"] == o["ledger"]["crossings"]
+    assert np.array_equal(g["tree"], o["tree"])
+
+
+@pytest.mark.parametrize("center", [(16.0, 16.0, 16.0), (16.5, 16.5, 16.5), (0.0, 0.0, 0.0), (31.75, 0.5, 15.0)])
+def test_geometry_mode_tree_bit_exact(arc, ctx, center):
+    """No termination: rays run to the box edge; tree and crossings must be identical."""
+    w = W.c1(n=32, center=center)
+    w.grid["x_hi"][...] = 1e-4  # thin, so the test is about geometry
+    g = run_gpu_trace(arc, ctx, w, schedule="batched", tree_cap=1 << 22, eps_term=0.0)
+    o = run_oracle(w, tree_cap=1 << 22, eps_term=0.0)
+    assert g["ledger"]["rays"] == o["ledger"]["rays"]
+    assert g["ledger"]["crossings"] == o["ledger"]["crossings"]
+    assert np.array_equal(g["tree"], o["tree"])
+    assert rate_errors(g, o)[0] <= GAMMA_REL_TOL
+
+
+def test_lognormal_ragged_parity(arc, ctx):
+    """H + He, three bands, non-cubic grid that spans several tiles and ends ragged."""
+    w = small_lognormal()
+    g = run_gpu_trace(arc, ctx, w)
+    o = run_oracle(w)
+    errs = rate_errors(g, o)
+    assert max(errs) <= GAMMA_REL_TOL, errs
+    assert max(rate_errors(g, o, "heat")) <= GAMMA_REL_TOL
+    assert conservation(g["ledger"]) <= CONSERVATION_TOL
+    # FP32 optical depths can settle a termination test differently from FP64 only
+    # when tau sits within rounding of the threshold: allow a handful of rays
+    assert abs(g["ledger"]["crossings"] - o["ledger"]["crossings"]) <= 1e-5 * o["ledger"]["crossings"] + 50
+
+
+def test_lognormal_geometry_tree_exact(arc, ctx):
+    w = small_lognormal(shape=(24, 20, 28), n_src=3, seed=4)
+    g = run_gpu_trace(arc, ctx, w, tree_cap=1 << 22, eps_term=0.0)
+    o = run_oracle(w, tree_cap=1 << 22, eps_term=0.0)
+    assert np.array_equal(g["tree"], o["tree"])
+    assert g["ledger"]["crossings"] == o["ledger"]["crossings"]
+    assert max(rate_errors(g, o)) <= GAMMA_REL_TOL
+
+
+def test_plain_equals_batched_bitwise_and_repeatable(arc, ctx):
+    w = small_lognormal(seed=33)
+    a = run_gpu_trace(arc, ctx, w, schedule="plain")
+    b = run_gpu_trace(arc, ctx, w, schedule="batched")
+    c = run_gpu_trace(arc, ctx, w, schedule="batched", tune_waves=2, tune_refill=1, tune_blocks=37)
+    d = run_gpu_trace(arc, ctx, w, schedule="batched")
+    assert np.array_equal(a["J"], b["J"])
+    assert np.array_equal(b["J"], c["J"])
+    assert np.array_equal(b["J"], d["J"])
+    assert np.array_equal(a["gamma"], b["gamma"])
+    assert a["ledger"]["crossings"] == b["ledger"]["crossings"] == c["ledger"]["crossings"]
+
+
+def test_source_subsets_sum_bitwise(arc, ctx):
+    """Integer sums: fields of disjoint source subsets add up to the full field exactly
+    when the fixed-point unit is the same (it is set from the full source list)."""
+    w = small_lognormal(n_src=6, seed=8)
+    full = run_gpu_trace(arc, ctx, w)
+    u = full["ledger"]["u_j"]
+    parts = [run_gpu_trace(arc, ctx, w.subset(idx), u_j_override=max(u)) for idx in ([0, 2, 4], [1, 3, 5])]
+    ref = run_gpu_trace(arc, ctx, w, u_j_override=max(u))
+    assert np.array_equal(parts[0]["J"] + parts[1]["J"], ref["J"])
+
+
+def test_precision_variants_against_oracle(arc, ctx):
+    w = small_lognormal(seed=12)
+    o = run_oracle(w)
+    comp = max(rate_errors(run_gpu_trace(arc, ctx, w, precision="fp32_comp"), o))
+    plain = max(rate_errors(run_gpu_trace(arc, ctx, w, precision="fp32_plain"), o))
+    assert comp <= GAMMA_REL_TOL
+    assert plain >= comp
+
+
+def test_empty_and_degenerate_inputs(arc, ctx):
+    w = W.c1(n=16)
+    empty = w.subset(np.array([], dtype=int))
+    g = run_gpu_trace(arc, ctx, empty)
+    assert np.all(g["gamma"] == 0) and np.all(g["J"] == 0)
+    assert g["ledger"]["crossings"] == 0 and g["ledger"]["emitted"] == 0
+    # one-cell grid, no splits
+    one = W.c1(n=1, center=(0.5, 0.5, 0.5))
+    g = run_gpu_trace(arc, ctx, one, max_level=0)
+    o = run_oracle(one, max_level=0)
+    assert g["ledger"]["crossings"] == o["ledger"]["crossings"] == 12
+    assert rate_errors(g, o)[0] <= GAMMA_REL_TOL
+    # co-located sources
+    two = W.c1(n=16)
+    two.sources = {"pos": np.array([[8.0, 8.0, 8.0]] * 3), "ndot": np.array([1e48, 2e48, 3e48])}
+    g = run_gpu_trace(arc, ctx, two)
+    o = run_oracle(two)
+    assert rate_errors(g, o)[0] <= GAMMA_REL_TOL
+
+
+def test_invalid_inputs_are_rejected(arc, ctx):
+    import torch
+
+    w = W.c1(n=8)
+    g = arc.device_grid(w.grid)
+    gamma = torch.empty((3, 8, 8, 8), device="cuda")
+    heat = torch.empty_like(gamma)
+
+    def call(**kw):
+        args = dict(grid=g, sources=w.sources, bins=w.bins, dt=w.dt, gamma=gamma, heat=heat, level0=0)
+        args.update(kw)
+        return ctx.trace(**args)
+
+    with pytest.raises(arc.ArcError) as e:
+        call(sources={"pos": np.array([[4.1, 4.0, 4.0]]), "ndot": np.array([1e48])})
+    assert e.value.name == "ARC_E_RANGE"
+    with pytest.raises(arc.ArcError) as e:
+        call(sources={"pos": np.array([[8.0, 4.0, 4.0]]), "ndot": np.array([1e48])})
+    assert e.value.name == "ARC_E_RANGE"
+    bad = dict(w.bins, sigma=np.array([[0.0, 0.0, 0.0]]))
+    with pytest.raises(arc.ArcError) as e:
+        call(bins=bad)
+    assert e.value.name == "ARC_E_RANGE"
+    g2 = dict(g, x_hi=g["x_hi"].clone())
+    g2["x_hi"][0, 0, 0] = 1.5
+    with pytest.raises(arc.ArcError) as e:
+        call(grid=g2)
+    assert e.value.name == "ARC_E_RANGE"
+    with pytest.raises(arc.ArcError) as e:
+        call(u_j_override=1.0)
+    assert e.value.name == "ARC_E_OVERFLOW"
+    with pytest.raises(arc.ArcError) as e:
+        call(schedule=7)
+    assert e.value.name == "ARC_E_ARG"
+    # the context is still usable
+    led = call()
+    assert led["crossings"] > 0
+
+
+# ---------------------------------------------------------------------------------
+# Chemistry
+# ---------------------------------------------------------------------------------
+def gpu_chem(arc, ctx, w, gamma, heat, state=None):
+    import torch
+
+    g = arc.device_grid(dict(w.grid, **(state or {})))
+    st = ctx.chem_step(g, torch.from_numpy(gamma).cuda(), torch.from_numpy(heat).cuda(), w.dt, **w.chem)
+    return {k: g[k].cpu().numpy() for k in ("x_hi", "x_hei", "x_heii", "temp")}, st
+
+
+@pytest.mark.parametrize("which", ["c1", "lognormal"])
+def test_chemistry_parity(arc, ctx, which):
+    w = W.c1() if which == "c1" else small_lognormal(seed=5)
+    tr = run_gpu_trace(arc, ctx, w)
+    gpu, st = gpu_chem(arc, ctx, w, tr["gamma"], tr["heat"])
+    ora = oracle.chem(w.grid, w.state(), tr["gamma"].astype(np.float64), tr["heat"].astype(np.float64), w.dt, w.chem)
+    for k in ("x_hi", "x_hei", "x_heii"):
+        assert np.abs(gpu[k] - ora[k]).max() <= FRACTION_TOL, k
+    assert np.max(np.abs(gpu["temp"] / ora["temp"] - 1)) <= 1e-3
+    assert st["sub_total"] == pytest.approx(ora["nsub"].sum(), rel=0.02)
+    assert st["capped"] == 0
+
+
+def test_full_step_parity_c1(arc, ctx):
+    """Trace + chemistry on each side, then compare the ionised fractions."""
+    w = W.c1()
+    tr = run_gpu_trace(arc, ctx, w)
+    gpu, _ = gpu_chem(arc, ctx, w, tr["gamma"], tr["heat"])
+    o = run_oracle(w)
+    ora = oracle.chem(w.grid, w.state(), o["gamma"], o["heat"], w.dt, w.chem)
+    assert np.abs(gpu["x_hi"] - ora["x_hi"]).max() <= FRACTION_TOL
+
+
+@pytest.mark.slow
+def test_c2_config_parity(arc, ctx):
+    """128^3, 16 sources, H + He, three bands (the second benchmark configuration)."""
+    w = W.config(1)
+    g = run_gpu_trace(arc, ctx, w)
+    o = run_oracle(w)
+    errs = rate_errors(g, o)
+    assert max(errs) <= GAMMA_REL_TOL, errs
+    assert conservation(g["ledger"]) <= CONSERVATION_TOL
+    gp = run_gpu_trace(arc, ctx, w, schedule="plain")
+    assert np.array_equal(gp["J"], g["J"])
