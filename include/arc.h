@@ -137,6 +137,7 @@ typedef struct {
     double u_j[4];         /* fixed-point unit of each bin [photons/s * cell] */
     double ms_trace;       /* device time of the trace kernels [ms] */
     double ms_total;       /* device time of the whole call [ms] */
+    double ms_kernel;      /* batched: device time of the persistent trace kernel [ms] */
 } arc_ledger;
 
 /* One ray-tracing pass (a whole RT step's radiation field). `out` receives the rates;

@@ -61,7 +61,7 @@ class Ledger(C.Structure):
                 ("crossings", C.c_uint64), ("rays", C.c_uint64), ("splits", C.c_uint64),
                 ("terminated", C.c_uint64), ("escaped_rays", C.c_uint64), ("spills", C.c_uint64),
                 ("tree_count", C.c_int64), ("u_j", C.c_double * 4), ("ms_trace", C.c_double),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("ms_kernel", C.c_double)]
 
 
 class ChemParams(C.Structure):

@@ -48,7 +48,8 @@ struct arc_ctx {
     uint32_t* u32 = nullptr;                  // [0] n_out, [1] queue head
     int* errflag = nullptr;
     unsigned long long* chem_stats = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool timed_kernel = false;  // ev[4], ev[5] bracket the dominant trace kernel
     // last trace
     int last_nb = 0, last_nbp = 0;
     size_t last_ncell = 0;
@@ -207,7 +208,7 @@ arc_status arc_create(int32_t device, arc_ctx** out)
               hipMalloc((void**)&c->u32, 4 * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void**)&c->errflag, sizeof(int)) == hipSuccess &&
               hipMalloc((void**)&c->chem_stats, 4 * sizeof(unsigned long long)) == hipSuccess;
-    for (int i = 0; i < 4 && ok; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
+    for (int i = 0; i < 6 && ok; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
     if (!ok) {
         arc_destroy(c);
         return ARC_E_NOMEM;
@@ -224,7 +225,7 @@ void arc_destroy(arc_ctx* c)
                     c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 6; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     delete c;
 }
@@ -354,6 +355,7 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     A.tree_cap = p->tree_out ? p->tree_cap : 0;
 
     HIP_TRY(c, hipEventRecord(c->ev[1], st));
+    c->timed_kernel = false;
     const uint32_t npix0 = 12u << (2 * p->level0);
     if (s->n > 0 && p->schedule == ARC_SCHED_PLAIN) {
         // Section 2.1 iii: one source at a time, one HEALPix level per launch; the host
@@ -448,8 +450,11 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
             cur = 1 - cur;
         }
         HIP_TRY(c, launch_set_u32(c->u32 + 1, 0u, st));
+        HIP_TRY(c, hipEventRecord(c->ev[4], st));
+        c->timed_kernel = true;
         HIP_TRY(c, launch_trace_persistent(A, p->precision, c->rays[cur], cnt + ((litem - p->level0) & 1), c->u32 + 1,
                                            c->spill, spill_cap, blocks, waves, refill, st));
+        HIP_TRY(c, hipEventRecord(c->ev[5], st));
     }
     HIP_TRY(c, hipEventRecord(c->ev[2], st));
 
@@ -509,6 +514,11 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
         ledger->ms_trace = ms;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
         ledger->ms_total = ms;
+        ledger->ms_kernel = 0;
+        if (c->timed_kernel) {
+            HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[4], c->ev[5]));
+            ledger->ms_kernel = ms;
+        }
     }
     return ARC_OK;
 }

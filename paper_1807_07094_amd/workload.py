@@ -176,29 +176,6 @@ def white_noise(shape, seed: int, threads: int = 16) -> np.ndarray:
     return out
 
 
-def smooth_periodic(field: np.ndarray, sigma_cells: float, device=None) -> np.ndarray:
-    """Periodic Gaussian smoothing (FFT, float64) on `device` (torch) or the CPU."""
-    import torch
-
-    dev = torch.device(device) if device is not None else torch.device("cpu")
-    f = torch.from_numpy(field).to(dev)
-    shp = f.shape
-    fk = torch.fft.rfftn(f)
-    del f
-    for axis, n in enumerate(shp):
-        if axis == len(shp) - 1:
-            k = torch.fft.rfftfreq(n, device=dev, dtype=torch.float64)
-        else:
-            k = torch.fft.fftfreq(n, device=dev, dtype=torch.float64)
-        filt = torch.exp(-0.5 * (2 * math.pi * k * sigma_cells) ** 2)
-        view = [1] * len(shp)
-        view[axis] = -1
-        fk *= filt.view(view)
-    out = torch.fft.irfftn(fk, s=shp)
-    del fk
-    return out.cpu().numpy()
-
-
 def _lattice_positions(cells_flat: np.ndarray, shape, seed: int) -> np.ndarray:
     nz, ny, nx = shape
     z, rem = np.divmod(cells_flat, ny * nx)
@@ -246,16 +223,18 @@ def c1(n: int = 64, box_kpc: float = 6.6, center=None, ndot: float = 5e48, level
     )
 
 
-def _he_workload(name, n_h, n_src, seed, source_cells, dt_myr, level0, eps_term) -> Workload:
+def _he_workload(name, n_h, n_src, seed, source_cells, dt_myr, level0, eps_term, cand=None) -> Workload:
     shape = n_h.shape
     y_he = 0.08
     ncell = n_h.size
     if source_cells == "uniform":
         cells = _rng(seed, 1).choice(ncell, size=n_src, replace=False)
-    else:  # biased to the densest 1% of cells
-        flat = n_h.reshape(-1)
-        thr = np.partition(flat, ncell - max(1, ncell // 100))[ncell - max(1, ncell // 100)]
-        cand = np.flatnonzero(flat >= thr)
+    else:  # biased to the densest 1% of cells (cells at or above the 99th percentile)
+        if cand is None:
+            flat = n_h.reshape(-1)
+            k = max(1, ncell // 100)
+            thr = np.partition(flat, ncell - k)[ncell - k]
+            cand = np.flatnonzero(flat >= thr)
         cells = cand[_rng(seed, 1).choice(cand.size, size=n_src, replace=False)]
     grid = {"n_h": n_h.astype(np.float32), "cell_cm": COSMIC_CELL_CM, "y_he": y_he}
     grid.update(_initial_state(shape, y_he))
@@ -282,13 +261,36 @@ def lognormal(n: int, n_src: int, seed: int, source_cells: str = "top1", dt_myr:
 
 def grf(n: int, n_src: int, seed: int, device=None, source_cells: str = "top1", dt_myr: float = 0.1,
         level0: int = 1, eps_term: float = 1e-6) -> Workload:
+    """Gaussian-random-field density; the field arithmetic runs in FP64 with torch on
+    `device` (the GPU for 1024^3), the noise comes from the seeded Philox streams."""
+    import torch
+
     shape = (n, n, n)
-    g = smooth_periodic(white_noise(shape, seed), 2.0, device)
+    dev = torch.device(device) if device is not None else torch.device("cpu")
+    f = torch.from_numpy(white_noise(shape, seed)).to(dev)
+    fk = torch.fft.rfftn(f)
+    del f
+    for axis in range(3):
+        k = (torch.fft.rfftfreq if axis == 2 else torch.fft.fftfreq)(n, device=dev, dtype=torch.float64)
+        view = [1, 1, 1]
+        view[axis] = -1
+        fk *= torch.exp(-0.5 * (2 * math.pi * k * 2.0) ** 2).view(view)
+    g = torch.fft.irfftn(fk, s=shape)
+    del fk
     g -= g.mean()
     g /= g.std()
-    n_h = 1e-3 * np.exp(0.5 * g - 0.125)
+    n_h = (1e-3 * torch.exp(0.5 * g - 0.125)).to(torch.float32)
     del g
-    return _he_workload(f"grf-{n}^3-{n_src}src-s{seed}", n_h, n_src, seed, source_cells, dt_myr, level0, eps_term)
+    cand = None
+    if source_cells != "uniform":
+        flat = n_h.reshape(-1)
+        kk = max(1, flat.numel() // 100)
+        thr = torch.topk(flat, kk, sorted=False).values.min()
+        cand = torch.nonzero(flat >= thr).flatten().cpu().numpy()
+    n_h_np = n_h.cpu().numpy()
+    del n_h
+    return _he_workload(f"grf-{n}^3-{n_src}src-s{seed}", n_h_np, n_src, seed, source_cells, dt_myr, level0, eps_term,
+                        cand=cand)
 
 
 def config(index: int, device=None) -> Workload:
