@@ -155,7 +155,53 @@ arc_status arc_get_field(arc_ctx* ctx, int64_t* dst, int64_t count, void* stream
 arc_status arc_healpix_dirs(arc_ctx* ctx, int32_t level, float* dst, void* stream);
 
 /* Chemistry (section 2.7 and 2.8). */
-#define ARC_CHEM_PLAIN 0
+#define ARC_CHEM_PLAIN 0      /* sub-cycled backward-difference solver in every cell */
+#define ARC_CHEM_MLP_GATED 1  /* learned step where its gate accepts the cell, plain elsewhere */
+#define ARC_CHEM_MLP_ONLY 2   /* learned step in every cell (evaluation of the network only) */
+
+/* Learned chemistry: a 5 -> 64 -> 64 -> 2 network (BF16 weights and activations, FP32
+ * accumulation on the matrix cores) that maps (n_H, x_HI, T, Gamma_HI, dt) to (x_HI', T')
+ * in place of the sub-cycled update of section 2.7. It does not see helium or the heating
+ * rates; its gate accepts a cell only when (1) the inputs fall inside the training range
+ * in a 8^5 occupancy bin with at least gate_min_count training samples whose held-out
+ * error (max of |x_HI' error| and relative T' error) is <= gate_tol, (2) the outputs are
+ * physical, and (3) helium is close to steady over dt. Other cells run the plain solver. */
+typedef struct arc_mlp arc_mlp;
+
+typedef struct {
+    int32_t epochs;        /* passes over the training samples */
+    int32_t batch;         /* minibatch size (multiple of 64 recommended) */
+    double lr;             /* Adam learning rate */
+    uint32_t seed;         /* initialisation and shuffling */
+    double val_frac;       /* share of the samples held out for the gate (0 < v < 1) */
+    void* stream;          /* hipStream_t, NULL = default stream */
+} arc_train_params;
+
+typedef struct {
+    double val_rmse_x;     /* held-out RMS error of x_HI' */
+    double val_rmse_logt;  /* held-out RMS error of log10 T' */
+    double val_max_err;    /* held-out max of the per-sample gate error */
+    int64_t n_train, n_val;
+    int64_t bins_used;     /* occupancy bins holding training samples */
+    double ms;             /* wall time of the training call [ms] */
+} arc_train_report;
+
+/* Create an untrained network owned by the caller (release with arc_mlp_destroy). */
+arc_status arc_mlp_create(arc_ctx* ctx, arc_mlp** out);
+void arc_mlp_destroy(arc_mlp* mlp);
+/* Train on m device samples: X [m][5] = (n_H [cm^-3], x_HI, T [K], Gamma_HI [1/s], dt [s]),
+ * Y [m][2] = (x_HI', T' [K]) from the plain solver. All inputs must be finite with
+ * n_H, T, dt > 0. Fits the standardisation, trains, then calibrates the gate on the
+ * held-out samples. */
+arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float* Y, int64_t m,
+                         const arc_train_params* params, arc_train_report* report);
+/* Network (weights, standardisation, gate) as a byte blob: with buf == NULL, *size
+ * receives the size; otherwise buf must hold *size bytes. */
+arc_status arc_mlp_save(const arc_mlp* mlp, void* buf, size_t* size);
+arc_status arc_mlp_load(arc_mlp* mlp, const void* buf, size_t size);
+/* Predictions for device samples X [m][5] (same units as training) into device P [m][2]
+ * = (x_HI', T' [K]), without the gate. */
+arc_status arc_mlp_predict(arc_ctx* ctx, const arc_mlp* mlp, const float* X, int64_t m, float* P, void* stream);
 
 typedef struct {
     int32_t isothermal;    /* 1: temperature fixed */
@@ -168,6 +214,9 @@ typedef struct {
     double t_floor;        /* minimum temperature [K] */
     int32_t mode;          /* ARC_CHEM_* */
     void* stream;          /* hipStream_t, NULL = default stream */
+    const arc_mlp* mlp;    /* trained network for the MLP modes */
+    double gate_tol;       /* MLP_GATED: largest accepted held-out bin error */
+    int32_t gate_min_count; /* MLP_GATED: smallest accepted training count per bin */
 } arc_chem_params;
 
 typedef struct {
@@ -176,6 +225,8 @@ typedef struct {
     int32_t sub_max;       /* largest sub-cycle count of a cell */
     int64_t capped;        /* cells that reached max_sub */
     double ms;             /* device time [ms] */
+    int64_t fallback;      /* MLP_GATED: cells handed to the plain solver */
+    double ms_mlp;         /* MLP modes: device time of the network and gate [ms] */
 } arc_chem_stats;
 
 /* Advance x_hi, x_hei, x_heii and temp of `grid` in place over dt [s] with the rates

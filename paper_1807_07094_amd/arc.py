@@ -67,12 +67,25 @@ class Ledger(C.Structure):
 class ChemParams(C.Structure):
     _fields_ = [("isothermal", C.c_int32), ("rates", C.c_int32), ("collisional", C.c_int32),
                 ("alpha_hii", C.c_double), ("eps", C.c_double), ("max_sub", C.c_int32), ("t_floor", C.c_double),
-                ("mode", C.c_int32), ("stream", C.c_void_p)]
+                ("mode", C.c_int32), ("stream", C.c_void_p), ("mlp", C.c_void_p), ("gate_tol", C.c_double),
+                ("gate_min_count", C.c_int32)]
 
 
 class ChemStats(C.Structure):
     _fields_ = [("cells", C.c_int64), ("sub_total", C.c_int64), ("sub_max", C.c_int32), ("capped", C.c_int64),
-                ("ms", C.c_double)]
+                ("ms", C.c_double), ("fallback", C.c_int64), ("ms_mlp", C.c_double)]
+
+
+class TrainParams(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("seed", C.c_uint32),
+                ("val_frac", C.c_double), ("stream", C.c_void_p)]
+
+
+class TrainReport(C.Structure):
+    _fields_ = [("val_rmse_x", C.c_double), ("val_rmse_logt", C.c_double), ("val_max_err", C.c_double),
+                ("n_train", C.c_int64), ("n_val", C.c_int64), ("bins_used", C.c_int64), ("ms", C.c_double)]
+
+CHEM_MODE = {"plain": 0, "mlp_gated": 1, "mlp_only": 2}
 
 
 def lib():
@@ -98,6 +111,19 @@ def lib():
         L.arc_chem_step.restype = C.c_int32
         L.arc_chem_step.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Rates), C.c_double,
                                     C.POINTER(ChemParams), C.POINTER(ChemStats)]
+        L.arc_mlp_create.restype = C.c_int32
+        L.arc_mlp_create.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
+        L.arc_mlp_destroy.restype = None
+        L.arc_mlp_destroy.argtypes = [C.c_void_p]
+        L.arc_mlp_train.restype = C.c_int32
+        L.arc_mlp_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.POINTER(TrainParams), C.POINTER(TrainReport)]
+        L.arc_mlp_save.restype = C.c_int32
+        L.arc_mlp_save.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]
+        L.arc_mlp_load.restype = C.c_int32
+        L.arc_mlp_load.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.arc_mlp_predict.restype = C.c_int32
+        L.arc_mlp_predict.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -199,11 +225,65 @@ class Context:
         return dst
 
     def chem_step(self, grid, gamma, heat, dt: float, isothermal=0, rates=1, collisional=1, alpha_hii=2.59e-13,
-                  eps=0.1, max_sub=100000, t_floor=1.0, mode=0, stream=None) -> dict:
+                  eps=0.1, max_sub=100000, t_floor=1.0, mode="plain", stream=None, mlp=None, gate_tol=1e-3,
+                  gate_min_count=16) -> dict:
         g = _grid(grid)
         r = Rates(_ptr(gamma), _ptr(heat))
         p = ChemParams(int(isothermal), int(rates), int(collisional), float(alpha_hii), float(eps), int(max_sub),
-                       float(t_floor), int(mode), _stream(stream))
+                       float(t_floor), CHEM_MODE[mode] if isinstance(mode, str) else int(mode), _stream(stream),
+                       mlp._h if mlp is not None else None, float(gate_tol), int(gate_min_count))
         st = ChemStats()
         self._check(lib().arc_chem_step(self._h, C.byref(g), C.byref(r), float(dt), C.byref(p), C.byref(st)))
         return {k: getattr(st, k) for k, _ in ChemStats._fields_}
+
+
+class MLP:
+    """arc_mlp: the learned chemistry network (owned; release with close())."""
+
+    def __init__(self, ctx: Context):
+        h = C.c_void_p()
+        rc = lib().arc_mlp_create(ctx._h, C.byref(h))
+        if rc != ARC_OK:
+            raise ArcError(rc, "arc_mlp_create failed")
+        self._h = h
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().arc_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train(self, X, Y, epochs=8, batch=1024, lr=2e-3, seed=1, val_frac=0.1, stream=None) -> dict:
+        """X: device float32 [m, 5] (n_H, x_HI, T, Gamma_HI, dt); Y: device float32 [m, 2] (x_HI', T')."""
+        p = TrainParams(int(epochs), int(batch), float(lr), int(seed), float(val_frac), _stream(stream))
+        rep = TrainReport()
+        self._ctx._check(lib().arc_mlp_train(self._ctx._h, self._h, _ptr(X), _ptr(Y), int(X.shape[0]), C.byref(p),
+                                             C.byref(rep)))
+        return {k: getattr(rep, k) for k, _ in TrainReport._fields_}
+
+    def predict(self, X, P, stream=None):
+        self._ctx._check(lib().arc_mlp_predict(self._ctx._h, self._h, _ptr(X), int(X.shape[0]), _ptr(P),
+                                               _stream(stream)))
+        return P
+
+    def save(self) -> bytes:
+        n = C.c_size_t(0)
+        rc = lib().arc_mlp_save(self._h, None, C.byref(n))
+        if rc != ARC_OK:
+            raise ArcError(rc, "arc_mlp_save size query failed")
+        buf = C.create_string_buffer(n.value)
+        rc = lib().arc_mlp_save(self._h, buf, C.byref(n))
+        if rc != ARC_OK:
+            raise ArcError(rc, "arc_mlp_save failed")
+        return buf.raw[: n.value]
+
+    def load(self, blob: bytes):
+        rc = lib().arc_mlp_load(self._h, blob, len(blob))
+        if rc != ARC_OK:
+            raise ArcError(rc, "arc_mlp_load failed")

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libarc.so")
-SOURCES = ["arc_kernels.hip", "arc_api.hip"]
+SOURCES = ["arc_kernels.hip", "arc_mlp.hip", "arc_api.hip", "arc_mlp_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -14,6 +14,7 @@
 
 #include "arc.h"
 #include "arc_kernels.h"
+#include "arc_mlp_host.h"
 
 using namespace arc;
 
@@ -48,10 +49,12 @@ struct arc_ctx {
     uint32_t* u32 = nullptr;                  // [0] n_out, [1] queue head
     int* errflag = nullptr;
     unsigned long long* chem_stats = nullptr;
+    uint32_t* fallback = nullptr;             // learned step: cells for the plain solver
+    size_t fallback_cap = 0;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool timed_kernel = false;  // ev[4], ev[5] bracket the dominant trace kernel
     // last trace
-    int last_nb = 0, last_nbp = 0;
+    int last_nb = 0, last_nbp = 0, last_nx = 0, last_ny = 0, last_nbx8 = 0, last_nby8 = 0;
     size_t last_ncell = 0;
     bool have_field = false;
 };
@@ -185,6 +188,20 @@ arc_status ensure_dirs(arc_ctx* c, int levels, hipStream_t st)
 
 }  // namespace
 
+namespace arc {
+int ctx_device(const arc_ctx* c) { return c->device; }
+arc_status ctx_fail(arc_ctx* c, arc_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+}  // namespace arc
+
 extern "C" {
 
 arc_status arc_create(int32_t device, arc_ctx** out)
@@ -222,7 +239,7 @@ void arc_destroy(arc_ctx* c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     void* bufs[] = {c->kappa, c->J, c->src, c->src_pos, c->src_ndot, c->dirs, c->rays[0], c->rays[1],
-                    c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats};
+                    c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats, c->fallback};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < 6; ++i)
@@ -259,6 +276,9 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     const int nb = b->nbins;
     const int nbp = nb == 1 ? 1 : (nb == 2 ? 2 : 4);
     const size_t ncell = (size_t)g->nx * g->ny * g->nz;
+    const int nbx8 = (g->nx + 7) / 8, nby8 = (g->ny + 7) / 8, nbz8 = (g->nz + 7) / 8;
+    const size_t nblocked = (size_t)nbx8 * nby8 * nbz8 * 512;  // cells of the blocked layout
+    if (nblocked > 2147483648ull) return fail(c, ARC_E_UNSUPPORTED, "blocked grid exceeds 2^31 cells");
 
     // Fixed-point unit per bin. One source deposits at most sqrt(3) S_b into a cell
     // (the photon rate through any sphere is at most S_b and a cell is at most sqrt(3)
@@ -283,9 +303,9 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
 
     // Buffers.
     {
-        const size_t kb = ncell * (nb == 1 ? sizeof(float) : sizeof(float4));
+        const size_t kb = nblocked * (nb == 1 ? sizeof(float) : sizeof(float4));
         HIP_TRY(c, grow(&c->kappa, &c->kappa_bytes, kb));
-        HIP_TRY(c, grow(&c->J, &c->J_bytes, ncell * nbp * sizeof(unsigned long long)));
+        HIP_TRY(c, grow(&c->J, &c->J_bytes, nblocked * nbp * sizeof(unsigned long long)));
         if (s->n > c->src_cap) {
             if (c->src) HIP_TRY(c, hipFree(c->src));
             if (c->src_pos) HIP_TRY(c, hipFree(c->src_pos));
@@ -308,6 +328,12 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
 
     OpacityArgs oa{};
     oa.nb = nb;
+    oa.nx = g->nx;
+    oa.ny = g->ny;
+    oa.nz = g->nz;
+    oa.nbx8 = nbx8;
+    oa.nby8 = nby8;
+    oa.nbz8 = nbz8;
     oa.ncell = (uint32_t)ncell;
     oa.L = g->cell_cm;
     oa.y = g->y_he;
@@ -337,6 +363,8 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     A.ny = g->ny;
     A.nz = g->nz;
     A.nb = nb;
+    A.nbx8 = nbx8;
+    A.nby8 = nby8;
     A.level0 = p->level0;
     A.lmax = lmax;
     const float base = split_base(p->rays_per_cell);
@@ -461,6 +489,10 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     FinalizeArgs fa{};
     fa.nb = nb;
     fa.nbp = nbp;
+    fa.nx = g->nx;
+    fa.ny = g->ny;
+    fa.nbx8 = nbx8;
+    fa.nby8 = nby8;
     fa.ncell = (uint32_t)ncell;
     const double L2 = g->cell_cm * g->cell_cm;
     for (int k = 0; k < nb; ++k) {
@@ -491,6 +523,10 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     c->last_nb = nb;
     c->last_nbp = nbp;
     c->last_ncell = ncell;
+    c->last_nx = g->nx;
+    c->last_ny = g->ny;
+    c->last_nbx8 = nbx8;
+    c->last_nby8 = nby8;
     c->have_field = true;
     if (errflag) return fail(c, ARC_E_RANGE, "grid values out of range (n_h <= 0, fraction outside [0,1] or non-finite)");
     if (cnt[kQueueOverflow]) return fail(c, ARC_E_QUEUE, "ray queue capacity exceeded (%llu rays dropped)", cnt[kQueueOverflow]);
@@ -530,7 +566,8 @@ arc_status arc_get_field(arc_ctx* c, int64_t* dst, int64_t count, void* stream)
     if (count < (int64_t)(c->last_ncell * c->last_nb)) return fail(c, ARC_E_ARG, "dst too small");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, launch_get_field(c->J, c->last_nb, c->last_nbp, (uint32_t)c->last_ncell, (long long*)dst, st));
+    HIP_TRY(c, launch_get_field(c->J, c->last_nb, c->last_nbp, c->last_nx, c->last_ny, c->last_nbx8, c->last_nby8,
+                                (uint32_t)c->last_ncell, (long long*)dst, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     return ARC_OK;
 }
@@ -575,7 +612,11 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     if (p->rates != 0 && p->rates != 1) return fail(c, ARC_E_ARG, "rates must be 0 or 1");
     if (p->rates == 0 && !(p->alpha_hii >= 0)) return fail(c, ARC_E_RANGE, "alpha_hii must be >= 0");
     if (!(p->t_floor > 0)) return fail(c, ARC_E_RANGE, "t_floor must be > 0");
-    if (p->mode != ARC_CHEM_PLAIN) return fail(c, ARC_E_UNSUPPORTED, "chemistry mode %d not available", p->mode);
+    if (p->mode != ARC_CHEM_PLAIN && p->mode != ARC_CHEM_MLP_GATED && p->mode != ARC_CHEM_MLP_ONLY)
+        return fail(c, ARC_E_ARG, "bad chemistry mode %d", p->mode);
+    if (p->mode != ARC_CHEM_PLAIN && (!p->mlp || !p->mlp->trained))
+        return fail(c, ARC_E_ARG, "the learned modes need a trained network");
+    if (p->mode == ARC_CHEM_MLP_GATED && !(p->gate_tol >= 0)) return fail(c, ARC_E_RANGE, "gate_tol must be >= 0");
     hipStream_t st = (hipStream_t)p->stream;
     HIP_TRY(c, hipSetDevice(c->device));
     ChemArgs a{};
@@ -597,9 +638,50 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     a.eps = p->eps;
     a.t_floor = p->t_floor;
     a.stats = c->chem_stats;
+    a.list = nullptr;
+    a.n_list = nullptr;
     HIP_TRY(c, launch_zero_u64(c->chem_stats, 4, st));
     HIP_TRY(c, hipEventRecord(c->ev[0], st));
-    HIP_TRY(c, launch_chem(a, st));
+    uint32_t n_fb = 0;
+    if (p->mode != ARC_CHEM_PLAIN) {
+        if (a.ncell > c->fallback_cap) {
+            if (c->fallback) HIP_TRY(c, hipFree(c->fallback));
+            c->fallback = nullptr;
+            c->fallback_cap = 0;
+            HIP_TRY(c, hipMalloc((void**)&c->fallback, (size_t)a.ncell * sizeof(uint32_t)));
+            c->fallback_cap = a.ncell;
+        }
+        HIP_TRY(c, launch_set_u32(c->u32 + 3, 0u, st));
+        mlp::InferArgs ia{};
+        ia.model = p->mlp->model;
+        ia.ncell = a.ncell;
+        ia.y = a.y;
+        ia.n_h = a.n_h;
+        ia.x_hi = a.x_hi;
+        ia.x_hei = a.x_hei;
+        ia.x_heii = a.x_heii;
+        ia.temp = a.temp;
+        ia.gamma = a.gamma;
+        ia.heat = a.heat;
+        ia.dt = dt;
+        ia.gated = p->mode == ARC_CHEM_MLP_GATED;
+        ia.gate_tol = (float)p->gate_tol;
+        ia.gate_min_count = (uint32_t)std::max(0, p->gate_min_count);
+        ia.t_floor = (float)p->t_floor;
+        ia.fallback = c->fallback;
+        ia.n_fallback = c->u32 + 3;
+        ia.collisional = p->rates == 1 ? p->collisional : 0;
+        HIP_TRY(c, mlp::launch_infer(ia, st));
+        HIP_TRY(c, hipEventRecord(c->ev[2], st));
+        if (p->mode == ARC_CHEM_MLP_GATED) {
+            a.list = c->fallback;
+            a.n_list = c->u32 + 3;
+            HIP_TRY(c, launch_chem(a, st));
+        }
+        HIP_TRY(c, hipMemcpyAsync(&n_fb, c->u32 + 3, sizeof n_fb, hipMemcpyDeviceToHost, st));
+    } else {
+        HIP_TRY(c, launch_chem(a, st));
+    }
     HIP_TRY(c, hipEventRecord(c->ev[1], st));
     unsigned long long cs[4];
     HIP_TRY(c, hipMemcpyAsync(cs, c->chem_stats, sizeof cs, hipMemcpyDeviceToHost, st));
@@ -612,6 +694,12 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
         float ms = 0;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
         stats->ms = ms;
+        stats->fallback = p->mode == ARC_CHEM_MLP_GATED ? (int64_t)n_fb : 0;
+        stats->ms_mlp = 0;
+        if (p->mode != ARC_CHEM_PLAIN) {
+            HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[2]));
+            stats->ms_mlp = ms;
+        }
     }
     return ARC_OK;
 }

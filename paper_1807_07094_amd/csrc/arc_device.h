@@ -19,6 +19,29 @@ constexpr float kDtauTermMin = 0.01f;  // a terminating crossing must be this th
 
 enum Event : int { kContinue = 0, kSplit = 1, kTerminate = 2, kEscape = 3 };
 
+constexpr uint32_t kNoCell = 0xFFFFFFFFu;
+
+// Cell layout of the opacity and the field: 8^3 blocks in x-fastest block order, Morton
+// order inside a block, so that the 2x2x2 neighbourhood of a cell shares a 128-byte
+// line of opacity (and two lines of field) and a block is 8 KB of opacity.
+__host__ __device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
+}
+__host__ __device__ __forceinline__ uint32_t blocked_index(int x, int y, int z, int nbx8, int nby8)
+{
+    const uint32_t b = ((uint32_t)(z >> 3) * (uint32_t)nby8 + (uint32_t)(y >> 3)) * (uint32_t)nbx8 + (uint32_t)(x >> 3);
+    const uint32_t m = spread3((uint32_t)x & 7u) | (spread3((uint32_t)y & 7u) << 1) | (spread3((uint32_t)z & 7u) << 2);
+    return (b << 9) | m;
+}
+
+// A crossing's deposit: the cell (blocked index) and the integer amount of every bin.
+template <int NB>
+struct Dep {
+    uint32_t cell;        // kNoCell: nothing to deposit
+    long long q[NB];
+};
+
 enum Counter : int {
     kCrossings = 0, kRays, kSplits, kTerminated, kEscapedRays, kSpills, kTreeCount, kQueueOverflow,
     kNumCounters
@@ -41,14 +64,24 @@ struct __align__(16) RayRec {
     float taulo[4];       // compensation terms
 };
 
+// The same ray in the compact form kept on a wave's stack (32 bytes for three bins).
+template <int NB>
+struct StackRec {
+    uint32_t src;
+    uint32_t lp;
+    float tau[NB];
+    float taulo[NB];
+};
+
 struct TraceArgs {
     int nx, ny, nz, nb;
+    int nbx8, nby8;            // 8^3 blocks per row and per column of the cell layout
     int level0, lmax;
     float tsplit[kMaxLevels];  // split radius of each level; +inf from lmax on
     float tau_term;            // +inf = never terminate
-    const float* kappa1;       // nb == 1: optical depth per cell length, [cell]
-    const float4* kappa4;      // nb > 1: [cell] (bins in x, y, z, w)
-    unsigned long long* J;     // fixed-point field [cell][nbp]
+    const float* kappa1;       // nb == 1: optical depth per cell length, [cell] (blocked order)
+    const float4* kappa4;      // nb > 1: [cell] (bins in x, y, z, w) (blocked order)
+    unsigned long long* J;     // fixed-point field [cell][nbp] (blocked order)
     int nbp;                   // padded bins per cell in J (1, 2 or 4)
     const SourceRec* src;
     const float4* dirs;        // HEALPix centres of every level, concatenated
@@ -59,12 +92,18 @@ struct TraceArgs {
     long long tree_cap;
 };
 
-// Per-lane ray state.
+// Per-lane ray state. Along axis i the ray meets its next cell boundary at
+// t_i = a_i / e_i, where e_i = |d_i| and a_i is the (exact, lattice-valued) distance of
+// that boundary from the source; crossing the boundary adds 1 to a_i. The blocked cell
+// index is the sum of one term per axis, refreshed only for the axes that move.
 template <int NB>
 struct Ray {
-    float d[3];
-    float xs[3];
-    int c[3];
+    float e[3];           // |d_i|
+    float ie[3];          // 1 / |d_i| (hardware reciprocal, within 1 ulp), 0 if d_i == 0
+    float a[3];           // next-boundary distance along each axis (exact)
+    int c[3];             // current cell
+    int step[3];          // +1, -1 or 0
+    uint32_t ix[3];       // per-axis terms of the blocked cell index
     float thi, tlo;       // current path length (double-float)
     float tend;           // split radius or +inf
     float tau[NB], taulo[NB];
@@ -122,6 +161,41 @@ __device__ __forceinline__ int start_index(float xs, float t0, float d)
     return k;
 }
 
+// Per-axis terms of blocked_index(): index = term(x, 0) + term(y, 1) + term(z, 2).
+__device__ __forceinline__ uint32_t axis_term(const TraceArgs& A, int i, int v)
+{
+    const uint32_t blk = (uint32_t)(v >> 3) << 9;
+    const uint32_t m = spread3((uint32_t)v & 7u) << i;
+    if (i == 0) return blk + m;
+    if (i == 1) return blk * (uint32_t)A.nbx8 + m;
+    return blk * (uint32_t)A.nbx8 * (uint32_t)A.nby8 + m;
+}
+
+// Non-negative float to the nearest int64 (v < 2^63): two exact 32-bit halves.
+__device__ __forceinline__ long long round_to_i64(float v)
+{
+    const float r = rintf(v);
+    const float hi = floorf(r * 2.3283064365386963e-10f);   // r / 2^32, exact scaling
+    const float lo = __builtin_fmaf(-hi, 4294967296.0f, r);  // exact remainder in [0, 2^32)
+    return (long long)(((unsigned long long)(uint32_t)hi << 32) | (unsigned long long)(uint32_t)lo);
+}
+
+// Mean attenuation over a segment of optical depth x: g(x) = (1 - e^-x) / x, g(0) = 1.
+// Below 0.25 a Taylor series (truncation < 5e-8 relative), above it the hardware
+// exponential (relative error < 1e-6).
+__device__ __forceinline__ float mean_atten(float x)
+{
+    const float series = __builtin_fmaf(
+        x, __builtin_fmaf(x, __builtin_fmaf(x, __builtin_fmaf(x, __builtin_fmaf(x, -1.0f / 720.0f, 1.0f / 120.0f), -1.0f / 24.0f), 1.0f / 6.0f), -0.5f),
+        1.0f);
+    if (x < 0.25f) return series;
+    const float em = __builtin_amdgcn_exp2f(-x * 1.4426950408889634f);
+    return (1.0f - em) * __builtin_amdgcn_rcpf(x);
+}
+
+// e^-tau with the hardware exponential (relative error ~1e-6 for tau up to ~80).
+__device__ __forceinline__ float transmission(float tau) { return __builtin_amdgcn_exp2f(-tau * 1.4426950408889634f); }
+
 // ---------------------------------------------------------------------------------
 // Per-ray operations.
 // ---------------------------------------------------------------------------------
@@ -138,21 +212,17 @@ __device__ __forceinline__ void record_tree(const TraceArgs& A, uint32_t src, ui
 // Load a ray: direction, source, start radius and start cell (section 2.1 iii a/c:
 // roots at radius 0, children at the parent's radius with their own direction).
 // Returns false (and books the escape) when the start point lies outside the grid.
-template <int NB>
-__device__ __forceinline__ bool ray_init(const TraceArgs& A, const RayRec& r, Ray<NB>& ray, LaneStats& st)
+template <int NB, class Rec>
+__device__ __forceinline__ bool ray_init(const TraceArgs& A, const Rec& r, Ray<NB>& ray, LaneStats& st)
 {
     ray.src = r.src;
     ray.lp = r.lp;
     const int level = (int)(r.lp >> kLevelShift);
     const uint32_t pix = r.lp & kPixMask;
     const float4 dv = A.dirs[A.dir_off[level] + pix];
-    ray.d[0] = dv.x;
-    ray.d[1] = dv.y;
-    ray.d[2] = dv.z;
+    const float d[3] = {dv.x, dv.y, dv.z};
     const SourceRec s = A.src[r.src];
-    ray.xs[0] = s.x;
-    ray.xs[1] = s.y;
-    ray.xs[2] = s.z;
+    const float xs[3] = {s.x, s.y, s.z};
     const float t0 = level == A.level0 ? 0.0f : A.tsplit[level - 1];
     ray.thi = t0;
     ray.tlo = 0.0f;
@@ -168,14 +238,20 @@ __device__ __forceinline__ bool ray_init(const TraceArgs& A, const RayRec& r, Ra
     bool inside = true;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        ray.c[i] = start_index(ray.xs[i], t0, ray.d[i]);
+        const int c = start_index(xs[i], t0, d[i]);
+        ray.c[i] = c;
+        ray.e[i] = fabsf(d[i]);
+        ray.ie[i] = d[i] != 0.0f ? __builtin_amdgcn_rcpf(ray.e[i]) : 0.0f;
+        ray.step[i] = d[i] > 0.0f ? 1 : (d[i] < 0.0f ? -1 : 0);
+        ray.a[i] = d[i] > 0.0f ? (float)(c + 1) - xs[i] : (d[i] < 0.0f ? xs[i] - (float)c : 1.0f);
         const int n = i == 0 ? A.nx : (i == 1 ? A.ny : A.nz);
-        inside = inside && ray.c[i] >= 0 && ray.c[i] < n;
+        inside = inside && c >= 0 && c < n;
+        ray.ix[i] = inside ? axis_term(A, i, c) : 0u;
     }
     if (!inside) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
-            st.esc[b] += (double)ray.w[b] * (double)expf(-(ray.tau[b] + ray.taulo[b]));
+            st.esc[b] += (double)ray.w[b] * (double)transmission(ray.tau[b] + ray.taulo[b]);
         st.escaped++;
     }
     return inside;
@@ -198,60 +274,75 @@ __device__ __forceinline__ void kappa_at(const TraceArgs& A, uint32_t cell, floa
 // One cell crossing (section 2.4): find the next x/y/z boundary (or the split radius),
 // deposit S (1 - e^-dtau) into the cell as S ds g(dtau) in fixed point (eq:ion per bin),
 // attenuate, then decide between continuing, splitting, terminating and escaping.
+//
+// Geometric decisions are exact: boundary times are compared through the reciprocal
+// products a_i / e_i, whose relative error is below 2e-7, and any comparison closer than
+// 1e-6 is settled exactly with cmp_prod (a_i e_j vs a_j e_i).
 template <int NB, int PREC>
-__device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneStats& st)
+__device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneStats& st, Dep<NB>& dep)
 {
-    float a[3], e[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        if (ray.d[i] > 0.0f) {
-            a[i] = (float)(ray.c[i] + 1) - ray.xs[i];
-            e[i] = ray.d[i];
-        } else if (ray.d[i] < 0.0f) {
-            a[i] = ray.xs[i] - (float)ray.c[i];
-            e[i] = -ray.d[i];
-        } else {
-            a[i] = 1.0f;
-            e[i] = 0.0f;
-        }
+    // (the winning axis is selected with conditional moves: a runtime index into the
+    // per-ray arrays would move them to scratch memory)
+    constexpr float kNear = 1.000001f;
+    const float t0 = ray.e[0] > 0.0f ? ray.a[0] * ray.ie[0] : INFINITY;
+    const float t1 = ray.e[1] > 0.0f ? ray.a[1] * ray.ie[1] : INFINITY;
+    const float t2 = ray.e[2] > 0.0f ? ray.a[2] * ray.ie[2] : INFINITY;
+    int w = t1 < t0 ? 1 : 0;
+    float tw = w ? t1 : t0;
+    if (t2 < tw) {
+        w = 2;
+        tw = t2;
     }
-    int w = -1;
-    int mask = 0;
+    int mask = 1 << w;
     bool at_end;
-    float nhi, nlo;
+    float aw = w == 0 ? ray.a[0] : (w == 1 ? ray.a[1] : ray.a[2]);
+    float ew = w == 0 ? ray.e[0] : (w == 1 ? ray.e[1] : ray.e[2]);
+    float iew = w == 0 ? ray.ie[0] : (w == 1 ? ray.ie[1] : ray.ie[2]);
     if constexpr (PREC == 0) {
-        // exact decisions: t_i < t_j  <=>  a_i e_j < a_j e_i
+        const bool near = (w != 0 && t0 <= tw * kNear) || (w != 1 && t1 <= tw * kNear) || (w != 2 && t2 <= tw * kNear);
+        if (near) {
+            // exact argmin and ties: t_i < t_j  <=>  a_i e_j < a_j e_i
+            int ww = -1;
+            float ab = 0.0f, eb = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-            if (e[i] > 0.0f && (w < 0 || cmp_prod(a[i], e[w], a[w], e[i]) < 0)) w = i;
+            for (int i = 0; i < 3; ++i) {
+                if (ray.e[i] > 0.0f && (ww < 0 || cmp_prod(ray.a[i], eb, ab, ray.e[i]) < 0)) {
+                    ww = i;
+                    ab = ray.a[i];
+                    eb = ray.e[i];
+                }
+            }
+            w = ww;
+            mask = 0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-            if (e[i] > 0.0f && cmp_prod(a[i], e[w], a[w], e[i]) == 0) mask |= 1 << i;
-        at_end = ray.tend < INFINITY && cmp_prod(ray.tend, e[w], a[w], 1.0f) <= 0;
-        if (at_end) {
-            nhi = ray.tend;
-            nlo = 0.0f;
-        } else {
-            nhi = a[w] / e[w];
-            nlo = __builtin_fmaf(-nhi, e[w], a[w]) / e[w];
+            for (int i = 0; i < 3; ++i)
+                if (ray.e[i] > 0.0f && cmp_prod(ray.a[i], eb, ab, ray.e[i]) == 0) mask |= 1 << i;
+            aw = ab;
+            ew = eb;
+            iew = w == 0 ? ray.ie[0] : (w == 1 ? ray.ie[1] : ray.ie[2]);
+            tw = aw * iew;
         }
+        if (ray.tend > tw * kNear)
+            at_end = false;
+        else if (ray.tend * kNear < tw)
+            at_end = true;
+        else
+            at_end = cmp_prod(ray.tend, ew, aw, 1.0f) <= 0;
     } else {
-        // plain FP32: compare rounded quotients
-        float t[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            t[i] = e[i] > 0.0f ? a[i] / e[i] : INFINITY;
-            if (e[i] > 0.0f && (w < 0 || t[i] < t[w])) w = i;
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            if (e[i] > 0.0f && t[i] == t[w]) mask |= 1 << i;
-        at_end = ray.tend <= t[w];
-        nhi = at_end ? ray.tend : t[w];
-        nlo = 0.0f;
+        if (w != 0 && t0 == tw) mask |= 1;
+        if (w != 1 && t1 == tw) mask |= 2;
+        if (w != 2 && t2 == tw) mask |= 4;
+        at_end = ray.tend <= tw;
     }
-    // segment length ds = t_next - t_cur (double-float difference rounded to float)
-    float ds;
+    // next path length as a double-float, and the segment length ds = t_next - t_cur
+    float nhi, nlo, ds;
+    if (at_end) {
+        nhi = ray.tend;
+        nlo = 0.0f;
+    } else {
+        nhi = tw;
+        nlo = PREC == 0 ? __builtin_fmaf(-nhi, ew, aw) * iew : 0.0f;
+    }
     if constexpr (PREC == 0) {
         const float s = nhi - ray.thi;
         const float bb = s - nhi;
@@ -260,21 +351,18 @@ __device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneSt
     } else {
         ds = nhi - ray.thi;
     }
-    const uint32_t cell = (uint32_t)ray.c[0] + (uint32_t)A.nx * ((uint32_t)ray.c[1] + (uint32_t)A.ny * (uint32_t)ray.c[2]);
+    const uint32_t cell = ray.ix[0] + ray.ix[1] + ray.ix[2];
     float kap[NB];
     kappa_at<NB>(A, cell, kap);
-    unsigned long long* Jc = A.J + (size_t)cell * (size_t)A.nbp;
+    dep.cell = cell;
     float dtau[NB];
     bool term = A.tau_term < INFINITY;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         dtau[b] = kap[b] * ds;
         const float taun = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-        const float T = expf(-taun);
-        const float g = dtau[b] > 0.0f ? -expm1f(-dtau[b]) / dtau[b] : 1.0f;
-        const float v = ((ray.w[b] * T) * ds) * g;
-        const long long q = __float2ll_rn(v);
-        if (q) atomicAdd(Jc + b, (unsigned long long)q);
+        const float v = ((ray.w[b] * transmission(taun)) * ds) * mean_atten(dtau[b]);
+        dep.q[b] = round_to_i64(v);
         if constexpr (PREC == 0) {
             const float s = ray.tau[b] + dtau[b];
             const float bb = s - ray.tau[b];
@@ -294,9 +382,7 @@ __device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneSt
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-            const float v = (ray.w[b] * expf(-taup)) / kap[b];
-            const long long q = __float2ll_rn(v);
-            if (q) atomicAdd(Jc + b, (unsigned long long)q);
+            dep.q[b] += round_to_i64((ray.w[b] * transmission(taup)) / kap[b]);
         }
         st.terminated++;
         return kTerminate;
@@ -305,16 +391,24 @@ __device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneSt
         st.splits++;
         return kSplit;
     }
+    bool inside = true;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-        if (mask & (1 << i)) ray.c[i] += ray.d[i] > 0.0f ? 1 : -1;
-    const bool inside = ray.c[0] >= 0 && ray.c[0] < A.nx && ray.c[1] >= 0 && ray.c[1] < A.ny && ray.c[2] >= 0 &&
-                        ray.c[2] < A.nz;
+    for (int i = 0; i < 3; ++i) {
+        if (mask & (1 << i)) {
+            const int c = ray.c[i] + ray.step[i];
+            ray.c[i] = c;
+            ray.a[i] += 1.0f;
+            const int n = i == 0 ? A.nx : (i == 1 ? A.ny : A.nz);
+            const bool in = c >= 0 && c < n;
+            inside = inside && in;
+            if (in) ray.ix[i] = axis_term(A, i, c);
+        }
+    }
     if (!inside) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-            st.esc[b] += (double)ray.w[b] * (double)expf(-taup);
+            st.esc[b] += (double)ray.w[b] * (double)transmission(taup);
         }
         st.escaped++;
         return kEscape;
@@ -337,6 +431,49 @@ __device__ __forceinline__ RayRec child_rec(const Ray<NB>& ray, int k)
         r.taulo[b] = b < NB ? ray.taulo[b] : 0.0f;
     }
     return r;
+}
+
+template <int NB>
+__device__ __forceinline__ StackRec<NB> child_stack(const Ray<NB>& ray, int k)
+{
+    StackRec<NB> r;
+    r.src = ray.src;
+    const uint32_t level = (ray.lp >> kLevelShift) + 1u;
+    r.lp = (level << kLevelShift) | (((ray.lp & kPixMask) << 2) + (uint32_t)k);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        r.tau[b] = ray.tau[b];
+        r.taulo[b] = ray.taulo[b];
+    }
+    return r;
+}
+
+// Fixed-point deposition of one crossing per lane, called by all 64 lanes together.
+// Atomic adds cost per distinct cache line an instruction touches, so the NB bins of a
+// lane's cell are issued by NB adjacent lanes of the same instruction: instruction k,
+// lane j adds bin (64k + j) mod NB of the crossing of lane (64k + j) / NB.
+template <int NB>
+__device__ __forceinline__ void deposit_wave(const TraceArgs& A, const Dep<NB>& d)
+{
+    if constexpr (NB == 1) {
+        if (d.cell != kNoCell && d.q[0] != 0) atomicAdd(A.J + d.cell, (unsigned long long)d.q[0]);
+    } else {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int s = 64 * k + lane;
+            const int item = s / NB, bin = s - item * NB;
+            const uint32_t cell = (uint32_t)__shfl((int)d.cell, item, 64);
+            long long q = 0;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const long long qb = __shfl(d.q[b], item, 64);
+                q = b == bin ? qb : q;
+            }
+            if (cell != kNoCell && q != 0)
+                atomicAdd(A.J + (size_t)cell * (size_t)A.nbp + (size_t)bin, (unsigned long long)q);
+        }
+    }
 }
 
 // Wave-level reduction and flush of lane statistics into the global counters.

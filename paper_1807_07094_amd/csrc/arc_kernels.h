@@ -10,6 +10,7 @@ namespace arc {
 
 struct OpacityArgs {
     int nb;
+    int nx, ny, nz, nbx8, nby8, nbz8;
     uint32_t ncell;
     double L, y;
     double sigma[kMaxBins][3];
@@ -23,6 +24,7 @@ struct OpacityArgs {
 
 struct FinalizeArgs {
     int nb, nbp;
+    int nx, ny, nbx8, nby8;
     uint32_t ncell;
     double gam[kMaxBins][3];   // u_J,b sigma_bS / L^2
     double hea[kMaxBins][3];   // u_J,b sigma_bS (E_b - E_S)^+ / L^2
@@ -44,6 +46,8 @@ struct ChemArgs {
     int isothermal, rates, collisional, max_sub;
     double alpha_hii, eps, t_floor;
     unsigned long long* stats;  // [0] sub total, [1] capped, [2] max
+    const uint32_t* list;       // optional: update only cells list[0 .. *n_list)
+    const uint32_t* n_list;
 };
 
 hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
@@ -62,8 +66,8 @@ hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* i
                                    int refill, hipStream_t s);
 int persistent_max_waves();
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
-hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, uint32_t ncell, long long* dst,
-                            hipStream_t s);
+hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, int nx, int ny, int nbx8, int nby8,
+                            uint32_t ncell, long long* dst, hipStream_t s);
 hipError_t launch_chem(const ChemArgs& a, hipStream_t s);
 
 }  // namespace arc

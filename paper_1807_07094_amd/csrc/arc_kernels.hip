@@ -14,6 +14,7 @@
 
 #include <math.h>
 
+#include "arc_chem.h"
 #include "arc_kernels.h"
 
 namespace arc {
@@ -69,35 +70,49 @@ hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s)
 // Opacity (section 2.2: tau per bin summed over HI, HeI, HeII) and field zeroing
 // (section 2.1 step i). One pass over the grid; invalid inputs raise a flag.
 // -------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t gather3(uint32_t m)
+{
+    return (m & 1u) | ((m >> 2) & 2u) | ((m >> 4) & 4u);
+}
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_opacity(OpacityArgs a)
 {
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
+    // one thread per cell of the blocked layout: contiguous writes, gathered reads
+    const uint32_t nblk = (uint32_t)a.nbx8 * (uint32_t)a.nby8 * (uint32_t)a.nbz8;
+    const uint32_t total = nblk << 9;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const uint32_t b = i >> 9, m = i & 511u;
+        const int x = (int)((b % (uint32_t)a.nbx8) * 8u + gather3(m));
+        const int y = (int)(((b / (uint32_t)a.nbx8) % (uint32_t)a.nby8) * 8u + gather3(m >> 1));
+        const int z = (int)((b / ((uint32_t)a.nbx8 * (uint32_t)a.nby8)) * 8u + gather3(m >> 2));
+        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
+        const uint32_t c = (uint32_t)x + (uint32_t)a.nx * ((uint32_t)y + (uint32_t)a.ny * (uint32_t)z);
         const float n = a.n_h[c], xh = a.x_hi[c], x1 = a.x_hei[c], x2 = a.x_heii[c];
         const bool ok = isfinite(n) && n > 0.0f && xh >= 0.0f && xh <= 1.0f && x1 >= 0.0f && x1 <= 1.0f &&
                         x2 >= 0.0f && x2 <= 1.0f;
         if (!ok) atomicOr(a.errflag, 1);
         float k[kMaxBins] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            k[b] = (float)(a.L * (double)n *
-                           (a.sigma[b][0] * (double)xh + a.y * (a.sigma[b][1] * (double)x1 + a.sigma[b][2] * (double)x2)));
+        for (int bb = 0; bb < NB; ++bb)
+            k[bb] = (float)(a.L * (double)n *
+                            (a.sigma[bb][0] * (double)xh + a.y * (a.sigma[bb][1] * (double)x1 + a.sigma[bb][2] * (double)x2)));
         if constexpr (NB == 1) {
-            a.kappa1[c] = k[0];
-            a.J[c] = 0ull;
+            a.kappa1[i] = k[0];
+            a.J[i] = 0ull;
         } else {
-            a.kappa4[c] = make_float4(k[0], k[1], k[2], k[3]);
-            unsigned long long* j = a.J + (size_t)c * a.nbp;
+            a.kappa4[i] = make_float4(k[0], k[1], k[2], k[3]);
+            unsigned long long* j = a.J + (size_t)i * a.nbp;
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                if (b < a.nbp) j[b] = 0ull;
+            for (int bb = 0; bb < 4; ++bb)
+                if (bb < a.nbp) j[bb] = 0ull;
         }
     }
 }
 
 hipError_t launch_opacity(const OpacityArgs& a, hipStream_t s)
 {
-    const unsigned g = grid_for(a.ncell, 256, 1u << 20);
+    const unsigned g = grid_for((size_t)a.nbx8 * a.nby8 * a.nbz8 * 512, 256, 1u << 20);
     switch (a.nb) {
         case 1: k_opacity<1><<<g, 256, 0, s>>>(a); break;
         case 2: k_opacity<2><<<g, 256, 0, s>>>(a); break;
@@ -265,16 +280,24 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
         const uint32_t i = base + threadIdx.x;
         int ev = kEscape;
         Ray<NB> ray;
+        bool act = false;
         if (i < n_in) {
             const RayRec r = in[i];
             record_tree<NB>(A, r.src, r.lp);
-            if (ray_init<NB>(A, r, ray, st)) {
-                do {
-                    ev = ray_step<NB, PREC>(A, ray, st);
-                } while (ev == kContinue);
-            } else {
-                ev = kEscape;
+            act = ray_init<NB>(A, r, ray, st);
+        }
+        // one crossing per lane per pass, so that the wave deposits together
+        while (__any(act)) {
+            Dep<NB> dep;
+            dep.cell = kNoCell;
+            if (act) {
+                const int e = ray_step<NB, PREC>(A, ray, st, dep);
+                if (e != kContinue) {
+                    ev = e;
+                    act = false;
+                }
             }
+            deposit_wave<NB>(A, dep);
         }
         const uint64_t m = __ballot(ev == kSplit);
         if (m) {
@@ -340,13 +363,15 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
                                                                RayRec* __restrict__ spill_all, uint32_t spill_cap,
                                                                int refill)
 {
-    __shared__ RayRec lds[WPB * kStackCap];
+    using SRec = StackRec<NB>;
+    __shared__ SRec lds[WPB * kStackCap];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint64_t lt = __lanemask_lt();
     const uint32_t n_items = *n_items_dev;
-    RayRec* stk = lds + wid * kStackCap;
-    RayRec* spill = spill_all + (size_t)(blockIdx.x * WPB + wid) * spill_cap;
+    SRec* stk = lds + wid * kStackCap;
+    // the spill area is sized in full records; compact records fit in it
+    SRec* spill = reinterpret_cast<SRec*>(spill_all + (size_t)(blockIdx.x * WPB + wid) * spill_cap);
     int base = 0;          // ring start (oldest entry), wave-uniform
     int top = 0;           // entries in the ring, wave-uniform
     uint32_t nspill = 0;   // wave-uniform
@@ -362,7 +387,7 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
         const bool pending = top > 0 || nspill > 0 || !qdone;
         if (nidle > 0 && pending && (nidle >= refill || nidle == 64)) {
             const int rank = __popcll(idle & lt);
-            RayRec r;
+            SRec r;
             bool got = false;
             int take = min(nidle, top);
             if (!has && rank < take) {
@@ -391,7 +416,14 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
                 } else {
                     const uint32_t avail = min((uint32_t)rem, n_items - b0);
                     if (!has && rank >= take && rank < take + (int)avail) {
-                        r = items[b0 + (uint32_t)(rank - take)];
+                        const RayRec& it = items[b0 + (uint32_t)(rank - take)];
+                        r.src = it.src;
+                        r.lp = it.lp;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            r.tau[b] = it.tau[b];
+                            r.taulo[b] = it.taulo[b];
+                        }
                         got = true;
                     }
                     if (b0 + (uint32_t)rem >= n_items) qdone = true;
@@ -407,7 +439,10 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
             continue;
         }
         int ev = kContinue;
-        if (has) ev = ray_step<NB, PREC>(A, ray, st);
+        Dep<NB> dep;
+        dep.cell = kNoCell;
+        if (has) ev = ray_step<NB, PREC>(A, ray, st, dep);
+        deposit_wave<NB>(A, dep);
         const uint64_t sp = __ballot(ev == kSplit);
         if (sp) {
             const int need = 3 * __popcll(sp);
@@ -431,11 +466,11 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
                 const int srank = __popcll(sp & lt);
 #pragma unroll
                 for (int k = 1; k < 4; ++k)
-                    stk[(base + top + 3 * srank + (k - 1)) & (kStackCap - 1)] = child_rec<NB>(ray, k);
+                    stk[(base + top + 3 * srank + (k - 1)) & (kStackCap - 1)] = child_stack<NB>(ray, k);
             }
             top += need;
             if (ev == kSplit) {
-                const RayRec c0 = child_rec<NB>(ray, 0);
+                const SRec c0 = child_stack<NB>(ray, 0);
                 record_tree<NB>(A, c0.src, c0.lp);
                 has = ray_init<NB>(A, c0, ray, st);
             }
@@ -488,15 +523,18 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a)
 {
     double absorbed = 0.0;
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
+        const uint32_t x = c % (uint32_t)a.nx, y = (c / (uint32_t)a.nx) % (uint32_t)a.ny,
+                       z = c / ((uint32_t)a.nx * (uint32_t)a.ny);
+        const uint32_t i = blocked_index((int)x, (int)y, (int)z, a.nbx8, a.nby8);
         double Jb[NB];
-        const unsigned long long* j = a.J + (size_t)c * a.nbp;
+        const unsigned long long* j = a.J + (size_t)i * a.nbp;
 #pragma unroll
         for (int b = 0; b < NB; ++b) Jb[b] = (double)(long long)j[b];
         float k[NB];
         if constexpr (NB == 1) {
-            k[0] = a.kappa1[c];
+            k[0] = a.kappa1[i];
         } else {
-            const float4 v = a.kappa4[c];
+            const float4 v = a.kappa4[i];
             k[0] = v.x;
             k[1] = v.y;
             if constexpr (NB > 2) k[2] = v.z;
@@ -532,16 +570,20 @@ hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_get_field(const unsigned long long* J, int nb, int nbp, uint32_t ncell, long long* dst)
+__global__ void k_get_field(const unsigned long long* J, int nb, int nbp, int nx, int ny, int nbx8, int nby8,
+                            uint32_t ncell, long long* dst)
 {
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x)
-        for (int b = 0; b < nb; ++b) dst[(size_t)b * ncell + c] = (long long)J[(size_t)c * nbp + b];
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
+        const uint32_t x = c % (uint32_t)nx, y = (c / (uint32_t)nx) % (uint32_t)ny, z = c / ((uint32_t)nx * (uint32_t)ny);
+        const uint32_t i = blocked_index((int)x, (int)y, (int)z, nbx8, nby8);
+        for (int b = 0; b < nb; ++b) dst[(size_t)b * ncell + c] = (long long)J[(size_t)i * nbp + b];
+    }
 }
 
-hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, uint32_t ncell, long long* dst,
-                            hipStream_t s)
+hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, int nx, int ny, int nbx8, int nby8,
+                            uint32_t ncell, long long* dst, hipStream_t s)
 {
-    k_get_field<<<grid_for(ncell, 256, 1u << 16), 256, 0, s>>>(J, nb, nbp, ncell, dst);
+    k_get_field<<<grid_for(ncell, 256, 1u << 16), 256, 0, s>>>(J, nb, nbp, nx, ny, nbx8, nby8, ncell, dst);
     return hipGetLastError();
 }
 
@@ -551,62 +593,15 @@ hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, uint32
 // lane. Rate coefficients and cooling in FP32, species and energy in FP64.
 // Coefficients: Hui & Gnedin (1997) fits with lambda = 2 T_i / T.
 // -------------------------------------------------------------------------------------
-namespace chem {
 
-constexpr float kTHI = 157807.0f, kTHeI = 285335.0f, kTHeII = 631515.0f;
-constexpr double kKB = 1.380649e-16;
-constexpr double kEV = 1.602176634e-12;
-
-struct Coef {
-    float a_hii, a_heii, a_heiii, k_hi, k_hei, k_heii;
-};
-
-__device__ __forceinline__ Coef coefficients(float T)
-{
-    const float lhi = 2.0f * kTHI / T, lhei = 2.0f * kTHeI / T, lheii = 2.0f * kTHeII / T;
-    const float t15 = powf(T, -1.5f);
-    Coef c;
-    c.a_hii = 2.753e-14f * powf(lhi, 1.5f) / powf(1.0f + powf(lhi / 2.740f, 0.407f), 2.242f);
-    const float diel = 1.90e-3f * t15 * expf(-0.75f * lheii / 2.0f) * (1.0f + 0.3f * expf(-0.15f * lheii / 2.0f));
-    c.a_heii = 1.26e-14f * powf(lhei, 0.750f) + diel;
-    c.a_heiii = 2.0f * 2.753e-14f * powf(lheii, 1.5f) / powf(1.0f + powf(lheii / 2.740f, 0.407f), 2.242f);
-    c.k_hi = 21.11f * t15 * expf(-lhi / 2.0f) * powf(lhi, -1.089f) / powf(1.0f + powf(lhi / 0.354f, 0.874f), 1.101f);
-    c.k_hei = 32.38f * t15 * expf(-lhei / 2.0f) * powf(lhei, -1.146f) / powf(1.0f + powf(lhei / 0.416f, 0.987f), 1.056f);
-    c.k_heii = 19.95f * t15 * expf(-lheii / 2.0f) * powf(lheii, -1.089f) / powf(1.0f + powf(lheii / 0.553f, 0.735f), 1.275f);
-    return c;
-}
-
-// Cooling per volume [erg cm^-3 s^-1]: recombination, collisional ionisation,
-// collisional excitation, bremsstrahlung. Rate coefficients in FP32, products in FP64.
-__device__ __forceinline__ double cooling(float T, const Coef& k, double ne, double nhi, double nhii, double nhei,
-                                          double nheii, double nheiii, int collisional)
-{
-    const float lhi = 2.0f * kTHI / T, lhei = 2.0f * kTHeI / T, lheii = 2.0f * kTHeII / T;
-    const float rec_hii = 3.435e-30f * T * powf(lhi, 1.970f) / powf(1.0f + powf(lhi / 2.250f, 0.376f), 3.720f);
-    const float rec_heii = 1.380649e-16f * T * 1.26e-14f * powf(lhei, 0.750f);
-    const float rec_heiii = 8.0f * 3.435e-30f * T * powf(lheii, 1.970f) / powf(1.0f + powf(lheii / 2.250f, 0.376f), 3.720f);
-    const float diel = 1.90e-3f * powf(T, -1.5f) * expf(-0.75f * lheii / 2.0f) * (1.0f + 0.3f * expf(-0.15f * lheii / 2.0f));
-    const double diel_cool = 0.75 * 54.418 * kEV * (double)diel;
-    double lam = ne * ((double)rec_hii * nhii + (double)rec_heii * nheii + (double)rec_heiii * nheiii + diel_cool * nheii);
-    if (collisional)
-        lam += ne * (13.598 * kEV * (double)k.k_hi * nhi + 24.587 * kEV * (double)k.k_hei * nhei +
-                     54.418 * kEV * (double)k.k_heii * nheii);
-    const float damp = 1.0f + sqrtf(T / 1e5f);
-    lam += ne * nhi * (double)(7.5e-19f * expf(-0.75f * lhi / 2.0f) / damp);
-    lam += ne * nheii * (double)(5.54e-17f * powf(T, -0.397f) * expf(-0.75f * lheii / 2.0f) / damp);
-    const float lt = log10f(T);
-    const float gff = 1.1f + 0.34f * expf(-(5.5f - lt) * (5.5f - lt) / 3.0f);
-    lam += (double)(1.42e-27f * gff * sqrtf(T)) * (nhii + nheii + 4.0 * nheiii) * ne;
-    return lam;
-}
-
-}  // namespace chem
 
 __global__ __launch_bounds__(256) void k_chem(ChemArgs a)
 {
     unsigned long long sub_total = 0, capped = 0;
     unsigned int sub_max = 0;
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
+    const uint32_t n_todo = a.list ? *a.n_list : a.ncell;
+    for (uint32_t ii = blockIdx.x * blockDim.x + threadIdx.x; ii < n_todo; ii += gridDim.x * blockDim.x) {
+        const uint32_t c = a.list ? a.list[ii] : ii;
         const double nh = a.n_h[c], nhe = a.y * nh;
         double nhi = nh * (double)a.x_hi[c], nhii = nh - nhi;
         double nhei = nhe * (double)a.x_hei[c], nheii = nhe * (double)a.x_heii[c];

@@ -1,0 +1,95 @@
+// arc_mlp.h -- learned chemistry step: a 5 -> 64 -> 64 -> 2 BF16 network on MFMA with FP32
+// accumulation that stands in for the per-cell sub-cycled update, with a per-cell gate and
+// the plain solver as fallback.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace arc {
+namespace mlp {
+
+constexpr int kIn = 5;       // log10 n_H, x_HI, log10 T, log10 Gamma_HI, log10 dt
+constexpr int kHid = 64;
+constexpr int kOut = 2;      // x_HI' (through a sigmoid), log10 T' (standardised)
+constexpr int kK1 = 32;      // layer-1 depth padded to one MFMA step
+constexpr int kOutP = 16;    // layer-3 width padded to one MFMA tile
+constexpr int kGate = 8;     // gate bins per input feature
+constexpr int kGateBins = kGate * kGate * kGate * kGate * kGate;
+constexpr float kGammaFloor = 1e-30f;
+
+// Offsets of the FP32 master parameters in one flat array.
+constexpr int kW1 = 0;                      // [kIn][kHid]
+constexpr int kB1 = kW1 + kIn * kHid;       // [kHid]
+constexpr int kW2 = kB1 + kHid;             // [kHid][kHid]
+constexpr int kB2 = kW2 + kHid * kHid;      // [kHid]
+constexpr int kW3 = kB2 + kHid;             // [kHid][kOut]
+constexpr int kB3 = kW3 + kHid * kOut;      // [kOut]
+constexpr int kNParams = kB3 + kOut;
+
+// Everything inference needs, in device memory.
+struct Model {
+    float in_mu[kIn], in_sd[kIn];   // feature standardisation
+    float lo[kIn], hi[kIn];         // training range of each feature (gate)
+    float t_mu, t_sd;               // standardisation of log10 T'
+    float b1[kHid], b2[kHid], b3[kOut];
+    __bf16 w1t[kHid][kK1];          // W1 transposed, rows padded with zeros
+    __bf16 w2t[kHid][kHid];         // W2 transposed
+    __bf16 w3t[kOutP][kHid];        // W3 transposed, rows >= kOut zero
+    uint32_t gate_count[kGateBins]; // training samples per bin
+    float gate_err[kGateBins];      // largest held-out error per bin (max of |dx| and |dT|/T)
+};
+
+struct InferArgs {
+    const Model* model;
+    uint32_t ncell;
+    double y;
+    const float* n_h;
+    float *x_hi, *x_hei, *x_heii, *temp;
+    const float *gamma, *heat;      // [3][ncell]
+    double dt;
+    int gated;                      // 0: accept every cell (evaluation)
+    float gate_tol;
+    uint32_t gate_min_count;
+    float t_floor;
+    uint32_t* fallback;             // cells that failed the gate
+    uint32_t* n_fallback;
+    int collisional;
+};
+
+hipError_t launch_infer(const InferArgs& a, hipStream_t s);
+
+// Training on standardised features F [m][kIn] and targets Y [m][2] (x_HI', standardised
+// log10 T'), minibatch rows given by idx.
+struct TrainArgs {
+    const Model* model;       // bf16 weights used by the forward pass
+    const float* F;
+    const float* Y;
+    const uint32_t* idx;      // sample order
+    uint32_t first, count;    // the minibatch: idx[first .. first + count)
+    float* partial;           // [waves][kNParams] gradient partial sums
+};
+hipError_t launch_train_grad(const TrainArgs& a, hipStream_t s);
+
+struct AdamArgs {
+    float* params;            // [kNParams] FP32 master
+    float* m;
+    float* v;
+    const float* partial;
+    int nwaves;
+    float lr, beta1, beta2, eps, inv_batch;
+    int step;
+    Model* model;             // refreshed bf16 images and biases
+};
+hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
+hipError_t launch_publish(const float* params, Model* model, hipStream_t s);
+
+// Forward pass only: predictions P [m][2] (x_HI', log10 T') for standardised features.
+hipError_t launch_predict(const Model* model, const float* F, uint32_t m, float* P, hipStream_t s);
+
+// Raw samples (n_H, x_HI, T, Gamma_HI, dt) and targets (x_HI', T') to features and
+// training targets; also min/max and sums for the standardisation.
+hipError_t launch_features(const float* X, const float* Y, uint32_t m, float* F, float* Yt, hipStream_t s);
+
+}  // namespace mlp
+}  // namespace arc

@@ -1,0 +1,477 @@
+// arc_mlp.hip -- learned chemistry step on gfx950 MFMA.
+//
+// Network: 5 -> 64 -> 64 -> 2, tanh hidden units, BF16 weights and activations, FP32
+// accumulation (v_mfma_f32_16x16x32_bf16). Inputs: log10 n_H, x_HI, log10 T, log10 Gamma_HI,
+// log10 dt, standardised. Outputs: x_HI' through a sigmoid and standardised log10 T'.
+// Helium is not an input: the gate accepts a cell only when its helium is close to steady.
+//
+//   k_infer       per cell: features, MFMA forward, gate; accepted cells are written,
+//                 rejected cells are appended to a list for the plain solver
+//   k_train_grad  quantisation-aware forward and backward of a minibatch (MFMA), one
+//                 gradient partial per wave (summed in fixed order: deterministic)
+//   k_adam        Adam update of the FP32 master parameters
+//   k_publish     BF16 transposed weight images for the MFMA operands
+//   k_predict     forward only, for validation and gate calibration
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "arc_chem.h"
+#include "arc_mlp.h"
+
+namespace arc {
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------------
+// MFMA building block. v_mfma_f32_16x16x32_bf16: D[16x16] += A[16x32] B[32x16]; lane l
+// supplies A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16] for i = 0..7 and
+// receives D[4 (l / 16) + r][l % 16] for r = 0..3.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// 8 elements (row, k0 .. k0+7) of a bf16 matrix with element strides sr (row) and sk (k).
+__device__ __forceinline__ bf16x8 frag(const __bf16* m, int row, int k0, int sr, int sk)
+{
+    bf16x8 v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = m[row * sr + (k0 + i) * sk];
+    return v;
+}
+
+// One 16x16 tile of D = A B over depth K (multiple of 32); A(m, k) = A[m sar + k sak],
+// B(k, n) = B[k sbk + n sbn]. Lane l receives D[m0 + 4 (l/16) + r][n0 + l % 16].
+__device__ __forceinline__ f32x4 tile_mm(const __bf16* A, int sar, int sak, const __bf16* B, int sbk, int sbn, int m0,
+                                         int n0, int K)
+{
+    const int lane = threadIdx.x & 63, r16 = lane & 15, q = lane >> 4;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const bf16x8 a = frag(A, m0 + r16, k0 + 8 * q, sar, sak);
+        const bf16x8 b = frag(B, n0 + r16, k0 + 8 * q, sbn, sbk);
+        acc = mfma(a, b, acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ float act(float x)  // tanh
+{
+    const float e = __builtin_amdgcn_exp2f(2.0f * 1.4426950408889634f * fminf(fmaxf(x, -15.0f), 15.0f));
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+__device__ __forceinline__ float sigmoid(float x)
+{
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * fminf(fmaxf(x, -80.0f), 80.0f)));
+}
+
+// Forward pass of 64 rows held in LDS: X [64][kK1] -> H (in place, [64][kHid]) -> O [64][2].
+// W1t [kHid][kK1], W2t [kHid][kHid], W3t [kOutP][kHid] and the biases are in LDS.
+// Every lane of the wave must call it. H1 (if given) keeps the first hidden layer.
+__device__ __forceinline__ void forward64(const __bf16* X, __bf16* H, __bf16* H1keep, float* O, const __bf16* w1t,
+                                          const __bf16* w2t, const __bf16* w3t, const float* b1, const float* b2,
+                                          const float* b3)
+{
+    const int lane = threadIdx.x & 63, r16 = lane & 15, q = lane >> 4;
+    // layer 1: [64 x 32] x [32 x 64]
+    for (int t = 0; t < 4; ++t) {
+        f32x4 d[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) d[nt] = tile_mm(X, kK1, 1, w1t, 1, kK1, 16 * t, 16 * nt, kK1);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * t + 4 * q + r, col = 16 * nt + r16;
+                const __bf16 h = (__bf16)act(d[nt][r] + b1[col]);
+                H[row * kHid + col] = h;
+                if (H1keep) H1keep[row * kHid + col] = h;
+            }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // layer 2: [64 x 64] x [64 x 64], written back over the rows it reads
+    for (int t = 0; t < 4; ++t) {
+        f32x4 d[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) d[nt] = tile_mm(H, kHid, 1, w2t, 1, kHid, 16 * t, 16 * nt, kHid);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * t + 4 * q + r, col = 16 * nt + r16;
+                H[row * kHid + col] = (__bf16)act(d[nt][r] + b2[col]);
+            }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // layer 3: [64 x 64] x [64 x 16]
+    for (int t = 0; t < 4; ++t) {
+        const f32x4 d = tile_mm(H, kHid, 1, w3t, 1, kHid, 16 * t, 0, kHid);
+        if (r16 < kOut)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) O[(16 * t + 4 * q + r) * kOut + r16] = d[r] + b3[r16];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Model weights into LDS (called by the whole block).
+struct SharedModel {
+    __bf16 w1t[kHid * kK1];
+    __bf16 w2t[kHid * kHid];
+    __bf16 w3t[kOutP * kHid];
+    float b1[kHid], b2[kHid], b3[kOut];
+};
+
+__device__ __forceinline__ void load_model(const Model* m, SharedModel& s)
+{
+    for (int i = threadIdx.x; i < kHid * kK1; i += blockDim.x) s.w1t[i] = (&m->w1t[0][0])[i];
+    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x) s.w2t[i] = (&m->w2t[0][0])[i];
+    for (int i = threadIdx.x; i < kOutP * kHid; i += blockDim.x) s.w3t[i] = (&m->w3t[0][0])[i];
+    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+        s.b1[i] = m->b1[i];
+        s.b2[i] = m->b2[i];
+    }
+    if (threadIdx.x < kOut) s.b3[threadIdx.x] = m->b3[threadIdx.x];
+}
+
+__device__ __forceinline__ float safe_log10(float v, float floor_) { return log10f(fmaxf(v, floor_)); }
+
+// ---------------------------------------------------------------------------------
+// Inference with the gate.
+// ---------------------------------------------------------------------------------
+constexpr int kInferWaves = 4;
+
+__global__ __launch_bounds__(64 * kInferWaves) void k_infer(InferArgs a)
+{
+    __shared__ SharedModel sm;
+    __shared__ __bf16 xs[kInferWaves][64 * kK1];
+    __shared__ __bf16 hs[kInferWaves][64 * kHid];
+    __shared__ float os[kInferWaves][64 * kOut];
+    const Model* M = a.model;
+    load_model(M, sm);
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t lt = __lanemask_lt();
+    const float ldt = log10f((float)a.dt);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x + 64 * wid; base < a.ncell; base += stride) {
+        const uint32_t c = base + lane;
+        const bool valid = c < a.ncell;
+        float f[kIn] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float nh = 1.0f, T = 1.0f;
+        if (valid) {
+            nh = a.n_h[c];
+            T = a.temp[c];
+            f[0] = log10f(nh);
+            f[1] = a.x_hi[c];
+            f[2] = log10f(T);
+            f[3] = safe_log10(a.gamma[c], kGammaFloor);
+            f[4] = ldt;
+        }
+        __bf16* X = xs[wid];
+#pragma unroll
+        for (int k = 0; k < kK1; ++k)
+            X[lane * kK1 + k] = (__bf16)(k < kIn && valid ? (f[k] - M->in_mu[k]) / M->in_sd[k] : 0.0f);
+        __builtin_amdgcn_wave_barrier();
+        forward64(X, hs[wid], nullptr, os[wid], sm.w1t, sm.w2t, sm.w3t, sm.b1, sm.b2, sm.b3);
+        bool accept = false;
+        float xn = 0.0f, Tn = 0.0f;
+        if (valid) {
+            const float o0 = os[wid][lane * kOut], o1 = os[wid][lane * kOut + 1];
+            xn = sigmoid(o0);
+            Tn = exp10f(o1 * M->t_sd + M->t_mu);
+            accept = true;
+            if (a.gated) {
+                // (1) inside the training range, in a bin with enough samples and a small
+                //     held-out error
+                uint32_t bin = 0;
+#pragma unroll
+                for (int k = kIn - 1; k >= 0; --k) {
+                    const float u = (f[k] - M->lo[k]) / (M->hi[k] - M->lo[k]);
+                    accept = accept && u >= 0.0f && u <= 1.0f;
+                    const int b = min(kGate - 1, max(0, (int)(u * kGate)));
+                    bin = bin * kGate + (uint32_t)b;
+                }
+                accept = accept && M->gate_count[bin] >= a.gate_min_count && M->gate_err[bin] <= a.gate_tol;
+                // (2) physical outputs
+                accept = accept && xn >= 0.0f && xn <= 1.0f && Tn >= a.t_floor && Tn < 1e9f;
+                // (3) helium close to steady over dt (the network does not see helium)
+                if (accept && a.y > 0.0) {
+                    const double nhd = nh, nhe = a.y * nhd;
+                    const double nhei = nhe * a.x_hei[c], nheii = nhe * a.x_heii[c];
+                    const double nheiii = fmax(0.0, nhe - nhei - nheii);
+                    const double nhii = nhd * (1.0 - a.x_hi[c]);
+                    const double ne = nhii + nheii + 2.0 * nheiii;
+                    const chem::Coef k = chem::coefficients(T);
+                    const double kc = a.collisional ? 1.0 : 0.0;
+                    const double dhei = (double)k.a_heii * ne * nheii -
+                                        ((double)a.gamma[(size_t)a.ncell + c] + kc * k.k_hei * ne) * nhei;
+                    const double dheiii = ((double)a.gamma[2 * (size_t)a.ncell + c] + kc * k.k_heii * ne) * nheii -
+                                          (double)k.a_heiii * ne * nheiii;
+                    accept = fabs(dhei) * a.dt <= 1e-3 * nhe && fabs(dheiii) * a.dt <= 1e-3 * nhe;
+                }
+            }
+        }
+        if (accept) {
+            a.x_hi[c] = xn;
+            a.temp[c] = Tn;
+        }
+        const uint64_t rej = __ballot(valid && !accept);
+        if (rej) {
+            const int leader = __ffsll((unsigned long long)rej) - 1;
+            uint32_t w0 = 0;
+            if (lane == leader) w0 = atomicAdd(a.n_fallback, (uint32_t)__popcll(rej));
+            w0 = __shfl(w0, leader, 64);
+            if (valid && !accept) a.fallback[w0 + (uint32_t)__popcll(rej & lt)] = c;
+        }
+    }
+}
+
+hipError_t launch_infer(const InferArgs& a, hipStream_t s)
+{
+    size_t blocks = (a.ncell + 64 * kInferWaves - 1) / (64 * kInferWaves);
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_infer<<<(unsigned)blocks, 64 * kInferWaves, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Forward only (validation, gate calibration).
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(64 * kInferWaves) void k_predict(const Model* M, const float* F, uint32_t m, float* P)
+{
+    __shared__ SharedModel sm;
+    __shared__ __bf16 xs[kInferWaves][64 * kK1];
+    __shared__ __bf16 hs[kInferWaves][64 * kHid];
+    __shared__ float os[kInferWaves][64 * kOut];
+    load_model(M, sm);
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (uint32_t base = blockIdx.x * blockDim.x + 64 * wid; base < m; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + lane;
+        const bool valid = i < m;
+#pragma unroll
+        for (int k = 0; k < kK1; ++k) xs[wid][lane * kK1 + k] = (__bf16)(k < kIn && valid ? F[(size_t)i * kIn + k] : 0.0f);
+        __builtin_amdgcn_wave_barrier();
+        forward64(xs[wid], hs[wid], nullptr, os[wid], sm.w1t, sm.w2t, sm.w3t, sm.b1, sm.b2, sm.b3);
+        if (valid) {
+            P[(size_t)i * 2] = sigmoid(os[wid][lane * kOut]);
+            P[(size_t)i * 2 + 1] = os[wid][lane * kOut + 1] * M->t_sd + M->t_mu;
+        }
+    }
+}
+
+hipError_t launch_predict(const Model* model, const float* F, uint32_t m, float* P, hipStream_t s)
+{
+    size_t blocks = (m + 64 * kInferWaves - 1) / (64 * kInferWaves);
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    k_predict<<<(unsigned)blocks, 64 * kInferWaves, 0, s>>>(model, F, m, P);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Features and targets of raw samples (n_H, x_HI, T, Gamma_HI, dt) -> (x_HI', T').
+// ---------------------------------------------------------------------------------
+__global__ void k_features(const float* X, const float* Y, uint32_t m, float* F, float* Yt)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        const float* x = X + (size_t)i * 5;
+        float* f = F + (size_t)i * kIn;
+        f[0] = log10f(x[0]);
+        f[1] = x[1];
+        f[2] = log10f(x[2]);
+        f[3] = safe_log10(x[3], kGammaFloor);
+        f[4] = log10f(x[4]);
+        Yt[(size_t)i * 2] = Y[(size_t)i * 2];
+        Yt[(size_t)i * 2 + 1] = log10f(Y[(size_t)i * 2 + 1]);
+    }
+}
+
+hipError_t launch_features(const float* X, const float* Y, uint32_t m, float* F, float* Yt, hipStream_t s)
+{
+    size_t blocks = (m + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    k_features<<<(unsigned)blocks, 256, 0, s>>>(X, Y, m, F, Yt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Training: gradient of the minibatch loss
+//   L = sum_s (sigmoid(o0) - x')^2 + (o1 - t')^2     (divided by the batch size in Adam)
+// through the same BF16 forward as inference. One wave per block, 64 samples per wave.
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
+{
+    __shared__ SharedModel sm;
+    __shared__ __bf16 w3pad[32 * kHid];  // W3t with zero rows to depth 32
+    __shared__ __bf16 X[64 * kK1];
+    __shared__ __bf16 H[64 * kHid];      // second hidden layer after the forward pass
+    __shared__ __bf16 H1[64 * kHid];
+    __shared__ __bf16 D2[64 * kHid];     // dL/dz2
+    __shared__ __bf16 D1[64 * kHid];     // dL/dz1
+    __shared__ __bf16 DO[64 * 32];       // dL/do, zero-padded to depth 32
+    __shared__ float O[64 * kOut];
+    load_model(a.model, sm);
+    for (int i = threadIdx.x; i < 32 * kHid; i += blockDim.x) w3pad[i] = i < kOutP * kHid ? sm.w3t[i] : (__bf16)0.0f;
+    __syncthreads();
+    const int lane = threadIdx.x, r16 = lane & 15, q = lane >> 4;
+    const uint32_t s_local = blockIdx.x * 64u + (uint32_t)lane;
+    const bool valid = s_local < a.count;
+    float y0 = 0.0f, y1 = 0.0f;
+    {
+        const uint32_t i = valid ? a.idx[a.first + s_local] : 0u;
+#pragma unroll
+        for (int k = 0; k < kK1; ++k) X[lane * kK1 + k] = (__bf16)(k < kIn && valid ? a.F[(size_t)i * kIn + k] : 0.0f);
+        if (valid) {
+            y0 = a.Y[(size_t)i * 2];
+            y1 = a.Y[(size_t)i * 2 + 1];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    forward64(X, H, H1, O, sm.w1t, sm.w2t, sm.w3t, sm.b1, sm.b2, sm.b3);
+    // output gradient
+    {
+        const float p = sigmoid(O[lane * kOut]);
+        const float g0 = valid ? 2.0f * (p - y0) * p * (1.0f - p) : 0.0f;
+        const float g1 = valid ? 2.0f * (O[lane * kOut + 1] - y1) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) DO[lane * 32 + k] = (__bf16)(k == 0 ? g0 : (k == 1 ? g1 : 0.0f));
+    }
+    __builtin_amdgcn_wave_barrier();
+    float* P = a.partial + (size_t)blockIdx.x * kNParams;
+    // dW3[k][n] = sum_s H2[s][k] dO[s][n]   (M = 64 k, N = 16 n, K = 64 s)
+    for (int t = 0; t < 4; ++t) {
+        const f32x4 d = tile_mm(H, 1, kHid, DO, 32, 1, 16 * t, 0, 64);
+        if (r16 < kOut)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P[kW3 + (16 * t + 4 * q + r) * kOut + r16] = d[r];
+    }
+    // dz2 = (dO W3^T) * (1 - H2^2)             (M = 64 s, N = 64 k, K = 32 n)
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 d = tile_mm(DO, 32, 1, w3pad, kHid, 1, 16 * t, 16 * nt, 32);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * t + 4 * q + r, col = 16 * nt + r16;
+                const float h = (float)H[row * kHid + col];
+                D2[row * kHid + col] = (__bf16)(d[r] * (1.0f - h * h));
+            }
+        }
+    __builtin_amdgcn_wave_barrier();
+    // dW2[k][n] = sum_s H1[s][k] dz2[s][n]     (M = 64, N = 64, K = 64)
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 d = tile_mm(H1, 1, kHid, D2, kHid, 1, 16 * t, 16 * nt, 64);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P[kW2 + (16 * t + 4 * q + r) * kHid + 16 * nt + r16] = d[r];
+        }
+    // dz1 = (dz2 W2^T) * (1 - H1^2)            (M = 64 s, N = 64 k, K = 64 n)
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 d = tile_mm(D2, kHid, 1, sm.w2t, kHid, 1, 16 * t, 16 * nt, 64);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * t + 4 * q + r, col = 16 * nt + r16;
+                const float h = (float)H1[row * kHid + col];
+                D1[row * kHid + col] = (__bf16)(d[r] * (1.0f - h * h));
+            }
+        }
+    __builtin_amdgcn_wave_barrier();
+    // dW1[k][n] = sum_s X[s][k] dz1[s][n]      (M = 16 k (5 used), N = 64, K = 64)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const f32x4 d = tile_mm(X, 1, kK1, D1, kHid, 1, 0, 16 * nt, 64);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = 4 * q + r;
+            if (k < kIn) P[kW1 + k * kHid + 16 * nt + r16] = d[r];
+        }
+    }
+    // bias gradients: column sums
+    {
+        float s1 = 0.0f, s2 = 0.0f;
+        for (int s = 0; s < 64; ++s) {
+            s1 += (float)D1[s * kHid + lane];
+            s2 += (float)D2[s * kHid + lane];
+        }
+        P[kB1 + lane] = s1;
+        P[kB2 + lane] = s2;
+        if (lane < kOut) {
+            float s3 = 0.0f;
+            for (int s = 0; s < 64; ++s) s3 += (float)DO[s * 32 + lane];
+            P[kB3 + lane] = s3;
+        }
+    }
+}
+
+hipError_t launch_train_grad(const TrainArgs& a, hipStream_t s)
+{
+    const unsigned waves = (a.count + 63) / 64;
+    k_train_grad<<<waves, 64, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+__global__ void k_adam(AdamArgs a)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNParams) return;
+    float g = 0.0f;
+    for (int w = 0; w < a.nwaves; ++w) g += a.partial[(size_t)w * kNParams + p];
+    g *= a.inv_batch;
+    const float m = a.beta1 * a.m[p] + (1.0f - a.beta1) * g;
+    const float v = a.beta2 * a.v[p] + (1.0f - a.beta2) * g * g;
+    a.m[p] = m;
+    a.v[p] = v;
+    const float mh = m / (1.0f - powf(a.beta1, (float)a.step));
+    const float vh = v / (1.0f - powf(a.beta2, (float)a.step));
+    a.params[p] -= a.lr * mh / (sqrtf(vh) + a.eps);
+}
+
+__global__ void k_publish(const float* P, Model* M)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kHid * kHid; i += gridDim.x * blockDim.x) {
+        const int n = i / kHid, k = i % kHid;  // w2t[n][k] = w2[k][n]
+        M->w2t[n][k] = (__bf16)P[kW2 + k * kHid + n];
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kHid * kK1; i += gridDim.x * blockDim.x) {
+        const int n = i / kK1, k = i % kK1;
+        M->w1t[n][k] = (__bf16)(k < kIn ? P[kW1 + k * kHid + n] : 0.0f);
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kOutP * kHid; i += gridDim.x * blockDim.x) {
+        const int n = i / kHid, k = i % kHid;
+        M->w3t[n][k] = (__bf16)(n < kOut ? P[kW3 + k * kOut + n] : 0.0f);
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kHid; i += gridDim.x * blockDim.x) {
+        M->b1[i] = P[kB1 + i];
+        M->b2[i] = P[kB2 + i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kOut) M->b3[threadIdx.x] = P[kB3 + threadIdx.x];
+}
+
+hipError_t launch_adam(const AdamArgs& a, hipStream_t s)
+{
+    k_adam<<<(kNParams + 255) / 256, 256, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_publish(a.params, a.model, s);
+}
+
+hipError_t launch_publish(const float* params, Model* model, hipStream_t s)
+{
+    k_publish<<<16, 256, 0, s>>>(params, model);
+    return hipGetLastError();
+}
+
+}  // namespace mlp
+}  // namespace arc
