@@ -271,18 +271,25 @@ __device__ __forceinline__ void kappa_at(const TraceArgs& A, uint32_t cell, floa
     }
 }
 
-// One cell crossing (section 2.4): find the next x/y/z boundary (or the split radius),
-// deposit S (1 - e^-dtau) into the cell as S ds g(dtau) in fixed point (eq:ion per bin),
-// attenuate, then decide between continuing, splitting, terminating and escaping.
+// A piece of a ray inside one cell: blocked cell index, length, and what happens at its
+// end (kContinue: next cell; kSplit: the split radius; kEscape: the ray leaves the grid).
+struct Seg {
+    uint32_t cell;
+    float ds;
+    int event;
+};
+
+// Geometry of the next segment (section 2.4: the step to the next x, y or z boundary, or
+// to the split radius), advancing the ray's position and cell.
 //
 // Geometric decisions are exact: boundary times are compared through the reciprocal
 // products a_i / e_i, whose relative error is below 2e-7, and any comparison closer than
-// 1e-6 is settled exactly with cmp_prod (a_i e_j vs a_j e_i).
+// 1e-6 is settled exactly with cmp_prod (a_i e_j vs a_j e_i). The winning axis is picked
+// with conditional moves (a runtime index into the per-ray arrays would move them to
+// scratch memory).
 template <int NB, int PREC>
-__device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneStats& st, Dep<NB>& dep)
+__device__ __forceinline__ Seg geom_next(const TraceArgs& A, Ray<NB>& ray)
 {
-    // (the winning axis is selected with conditional moves: a runtime index into the
-    // per-ray arrays would move them to scratch memory)
     constexpr float kNear = 1.000001f;
     const float t0 = ray.e[0] > 0.0f ? ray.a[0] * ray.ie[0] : INFINITY;
     const float t1 = ray.e[1] > 0.0f ? ray.a[1] * ray.ie[1] : INFINITY;
@@ -335,7 +342,7 @@ __device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneSt
         at_end = ray.tend <= tw;
     }
     // next path length as a double-float, and the segment length ds = t_next - t_cur
-    float nhi, nlo, ds;
+    float nhi, nlo;
     if (at_end) {
         nhi = ray.tend;
         nlo = 0.0f;
@@ -343,53 +350,21 @@ __device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneSt
         nhi = tw;
         nlo = PREC == 0 ? __builtin_fmaf(-nhi, ew, aw) * iew : 0.0f;
     }
+    Seg sg;
     if constexpr (PREC == 0) {
         const float s = nhi - ray.thi;
         const float bb = s - nhi;
         const float err = (nhi - (s - bb)) + (-ray.thi - bb);
-        ds = s + (err + (nlo - ray.tlo));
+        sg.ds = s + (err + (nlo - ray.tlo));
     } else {
-        ds = nhi - ray.thi;
+        sg.ds = nhi - ray.thi;
     }
-    const uint32_t cell = ray.ix[0] + ray.ix[1] + ray.ix[2];
-    float kap[NB];
-    kappa_at<NB>(A, cell, kap);
-    dep.cell = cell;
-    float dtau[NB];
-    bool term = A.tau_term < INFINITY;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        dtau[b] = kap[b] * ds;
-        const float taun = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-        const float v = ((ray.w[b] * transmission(taun)) * ds) * mean_atten(dtau[b]);
-        dep.q[b] = round_to_i64(v);
-        if constexpr (PREC == 0) {
-            const float s = ray.tau[b] + dtau[b];
-            const float bb = s - ray.tau[b];
-            ray.taulo[b] += (ray.tau[b] - (s - bb)) + (dtau[b] - bb);
-            ray.tau[b] = s;
-        } else {
-            ray.tau[b] += dtau[b];
-        }
-        const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-        term = term && taup >= A.tau_term && dtau[b] >= kDtauTermMin;
-    }
-    st.crossings++;
+    sg.cell = ray.ix[0] + ray.ix[1] + ray.ix[2];
     ray.thi = nhi;
     ray.tlo = nlo;
-    if (term) {
-        // absorb what is left in this cell: field += remaining photons / opacity
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-            dep.q[b] += round_to_i64((ray.w[b] * transmission(taup)) / kap[b]);
-        }
-        st.terminated++;
-        return kTerminate;
-    }
     if (at_end) {
-        st.splits++;
-        return kSplit;
+        sg.event = kSplit;
+        return sg;
     }
     bool inside = true;
 #pragma unroll
@@ -404,7 +379,52 @@ __device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneSt
             if (in) ray.ix[i] = axis_term(A, i, c);
         }
     }
-    if (!inside) {
+    sg.event = inside ? kContinue : kEscape;
+    return sg;
+}
+
+// Photons of one segment (section 2.4, eq:ion per bin): deposit S ds g(dtau) into the
+// cell in fixed point, attenuate (compensated tau), then apply the termination test and
+// the segment's own event. Returns kTerminate, kSplit, kEscape or kContinue.
+template <int NB, int PREC>
+__device__ __forceinline__ int deposit_seg(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
+                                           LaneStats& st, Dep<NB>& dep)
+{
+    dep.cell = sg.cell;
+    bool term = A.tau_term < INFINITY;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const float dtau = kap[b] * sg.ds;
+        const float taun = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+        const float v = ((ray.w[b] * transmission(taun)) * sg.ds) * mean_atten(dtau);
+        dep.q[b] = round_to_i64(v);
+        if constexpr (PREC == 0) {
+            const float s = ray.tau[b] + dtau;
+            const float bb = s - ray.tau[b];
+            ray.taulo[b] += (ray.tau[b] - (s - bb)) + (dtau - bb);
+            ray.tau[b] = s;
+        } else {
+            ray.tau[b] += dtau;
+        }
+        const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+        term = term && taup >= A.tau_term && dtau >= kDtauTermMin;
+    }
+    st.crossings++;
+    if (term) {
+        // absorb what is left in this cell: field += remaining photons / opacity
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+            dep.q[b] += round_to_i64((ray.w[b] * transmission(taup)) / kap[b]);
+        }
+        st.terminated++;
+        return kTerminate;
+    }
+    if (sg.event == kSplit) {
+        st.splits++;
+        return kSplit;
+    }
+    if (sg.event == kEscape) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
@@ -414,6 +434,47 @@ __device__ __forceinline__ int ray_step(const TraceArgs& A, Ray<NB>& ray, LaneSt
         return kEscape;
     }
     return kContinue;
+}
+
+// Segments whose geometry is computed ahead of their deposits (opacity loads in flight
+// per lane).
+#ifndef ARC_SEG_AHEAD
+#define ARC_SEG_AHEAD 2
+#endif
+constexpr int kSegAhead = ARC_SEG_AHEAD;
+
+// Up to K crossings of one lane per pass: the geometry of K segments is computed first
+// and their opacities are loaded together (K loads in flight per lane), then the
+// segments are deposited in order; `deposit` is called K times by the whole wave.
+// Returns the lane's final event of the pass (kContinue if the ray goes on).
+template <int NB, int PREC, int K, class DepositFn>
+__device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool active, LaneStats& st,
+                                          DepositFn deposit)
+{
+    Seg sg[K];
+    bool have[K];
+    bool go = active;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        have[j] = go;
+        if (go) {
+            sg[j] = geom_next<NB, PREC>(A, ray);
+            go = sg[j].event == kContinue;
+        }
+    }
+    float kap[K][NB];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (have[j]) kappa_at<NB>(A, sg[j].cell, kap[j]);
+    int ev = kContinue;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        Dep<NB> dep;
+        dep.cell = kNoCell;
+        if (have[j] && ev == kContinue) ev = deposit_seg<NB, PREC>(A, ray, sg[j], kap[j], st, dep);
+        deposit(dep);
+    }
+    return ev;
 }
 
 // Child k of a split ray: next level, pixel 4p + k, same optical depth (section 2.1 iii c).

@@ -286,18 +286,14 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
             record_tree<NB>(A, r.src, r.lp);
             act = ray_init<NB>(A, r, ray, st);
         }
-        // one crossing per lane per pass, so that the wave deposits together
+        // a few crossings per lane per pass; the wave deposits each crossing together
         while (__any(act)) {
-            Dep<NB> dep;
-            dep.cell = kNoCell;
-            if (act) {
-                const int e = ray_step<NB, PREC>(A, ray, st, dep);
-                if (e != kContinue) {
-                    ev = e;
-                    act = false;
-                }
+            const int e = trace_pass<NB, PREC, kSegAhead>(A, ray, act, st,
+                                                          [&](const Dep<NB>& d) { deposit_wave<NB>(A, d); });
+            if (act && e != kContinue) {
+                ev = e;
+                act = false;
             }
-            deposit_wave<NB>(A, dep);
         }
         const uint64_t m = __ballot(ev == kSplit);
         if (m) {
@@ -346,7 +342,7 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 // Batched schedule: after the first levels have been traced level by level (so that there
 // are enough independent subtrees), one persistent launch traces every remaining subtree.
 //
-// Each wave keeps 64 rays in flight, one per lane, and advances them one crossing per
+// Each wave keeps 64 rays in flight, one per lane, and advances them up to kSegAhead crossings per
 // iteration. Lanes whose ray ends are refilled (once at least `refill` lanes are idle)
 // from the wave's LDS stack, then from the wave's private spill area, then from the
 // global work queue of subtree roots (one atomic per refill). A splitting lane continues
@@ -438,11 +434,8 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
             if (top == 0 && nspill == 0 && qdone) break;
             continue;
         }
-        int ev = kContinue;
-        Dep<NB> dep;
-        dep.cell = kNoCell;
-        if (has) ev = ray_step<NB, PREC>(A, ray, st, dep);
-        deposit_wave<NB>(A, dep);
+        const int ev = trace_pass<NB, PREC, kSegAhead>(A, ray, has, st,
+                                                       [&](const Dep<NB>& d) { deposit_wave<NB>(A, d); });
         const uint64_t sp = __ballot(ev == kSplit);
         if (sp) {
             const int need = 3 * __popcll(sp);
