@@ -35,13 +35,21 @@ def main():
     ap.add_argument("--config", type=int, default=4, help="benchmark configuration 0..4 (4 = 1024^3, 16384 sources)")
     ap.add_argument("--schedule", default="batched", choices=["batched", "plain"])
     ap.add_argument("--precision", default="fp32_comp", choices=["fp32_comp", "fp32_plain"])
-    ap.add_argument("--no-chem", action="store_true", help="trace only (not a full step)")
+    ap.add_argument("--chem", default="mlp_gated", choices=["mlp_gated", "plain", "none"],
+                    help="chemistry of the step: learned step with the plain fallback, plain solver, or none")
+    ap.add_argument("--mlp-samples", type=int, default=1_000_000, help="training samples of the learned step")
+    ap.add_argument("--mlp-epochs", type=int, default=20)
+    ap.add_argument("--gate-tol", type=float, default=1e-3, help="gate: largest held-out error of a bin")
     ap.add_argument("--cpu-sample", type=int, default=16, help="sources in the oracle's timed sample (0 = skip)")
     ap.add_argument("--plain-sample", type=int, default=256, help="sources traced by the plain schedule (0 = skip)")
     ap.add_argument("--tune-waves", type=int, default=0)
     ap.add_argument("--tune-blocks", type=int, default=0)
     ap.add_argument("--tune-refill", type=int, default=0)
     ap.add_argument("--tune-item-level", type=int, default=0)
+    ap.add_argument("--tuned", action="store_true", help="autotuned launch shape (tuned before warm-up)")
+    ap.add_argument("--graph", type=int, default=1, help="1: replay the trace's recorded HIP graphs")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only copy this many GiB device to device (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -57,6 +65,15 @@ def main():
     from paper_1807_07094_amd import workload as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * 2**30) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+        return
     t0 = time.time()
     w = W.config(args.config, device="cuda")
     log(f"workload {w.name}: {w.shape} cells, {len(w.sources['ndot'])} sources, generated in {time.time() - t0:.1f}s")
@@ -73,9 +90,44 @@ def main():
                          rays_per_cell=w.trace["rays_per_cell"], eps_term=w.trace["eps_term"],
                          precision=args.precision, schedule=schedule, **kw)
 
+    net, mlp_info = None, None
+    if args.chem == "mlp_gated":
+        from paper_1807_07094_amd import learned
+
+        tt = time.perf_counter()
+        X, Y = learned.training_set(ctx, arc, n=args.mlp_samples)
+        ts = time.perf_counter() - tt
+        net = arc.MLP(ctx)
+        rep = net.train(X, Y, epochs=args.mlp_epochs, batch=1024, lr=2e-3, seed=3)
+        del X, Y
+        mlp_info = {"samples": args.mlp_samples, "sampling_s": round(ts, 2), "train_ms": round(rep["ms"], 1),
+                    "val_rmse_x": rep["val_rmse_x"], "val_rmse_logt": rep["val_rmse_logt"],
+                    "bins_used": rep["bins_used"], "gate_tol": args.gate_tol}
+        log(f"learned chemistry: {mlp_info}")
+    chem_kw = dict(w.chem)
+    if net is not None:
+        chem_kw.update(mode="mlp_gated", mlp=net, gate_tol=args.gate_tol)
+
+    schedule = args.schedule
+    tune_info = None
+    if args.tuned and args.schedule == "batched":
+        nsrc_all = len(w.sources["ndot"])
+        sub = w.subset(np.arange(0, nsrc_all, max(1, nsrc_all // 256)))
+        tt = time.perf_counter()
+        tune_info = ctx.autotune(g, sub.sources, w.bins, w.dt, gamma, heat, level0=w.trace["level0"],
+                                 rays_per_cell=w.trace["rays_per_cell"], eps_term=w.trace["eps_term"],
+                                 precision=args.precision)
+        tune_info["tuning_s"] = round(time.perf_counter() - tt, 2)
+        tune_info["tuning_sources"] = len(sub.sources["ndot"])
+        log(f"autotuned shape: {tune_info}")
+        schedule = "batched_tuned"
+        tune = {}
+    if schedule != "plain":
+        tune["graph"] = bool(args.graph)
+
     def step():
-        led = trace(g, w.sources, args.schedule, **tune)
-        cs = None if args.no_chem else ctx.chem_step(g, gamma, heat, w.dt, **w.chem)
+        led = trace(g, w.sources, schedule, **tune)
+        cs = None if args.chem == "none" else ctx.chem_step(g, gamma, heat, w.dt, **chem_kw)
         return led, cs
 
     for i in range(args.warmup):
@@ -115,22 +167,41 @@ def main():
     extra = {"trace_crossings_per_s": round(per_launch / (float(np.mean([l["ms_total"] for l in leds])) * 1e-3), 1),
              "kernel_crossings_per_s": round(per_launch / (kms * 1e-3), 1),
              "conservation": cons, "crossings_per_step": per_launch}
+    if tune_info is not None:
+        extra["autotune"] = tune_info
     if chems[0] is not None:
         extra["chem_ms"] = round(float(np.mean([c["ms"] for c in chems])), 2)
+    if net is not None:
+        # the plain solver judges the learned step: both from the same state and rates
+        fields = ("x_hi", "x_hei", "x_heii", "temp")
+        keep = {k: g[k].clone() for k in fields}
+        cg = ctx.chem_step(g, gamma, heat, w.dt, **chem_kw)
+        got = {k: g[k].clone() for k in fields}
+        for k in fields:
+            g[k].copy_(keep[k])
+        cp = ctx.chem_step(g, gamma, heat, w.dt, **w.chem)
+        dx = float((got["x_hi"] - g["x_hi"]).abs().max())
+        dT = float(((got["temp"] - g["temp"]) / g["temp"]).abs().max())
+        mlp_info.update(accepted_frac=round(1.0 - cg["fallback"] / cg["cells"], 4), max_abs_dx_hi=dx,
+                        max_rel_dT=dT, ms_gated=round(cg["ms"], 2), ms_mlp=round(cg["ms_mlp"], 2),
+                        ms_plain=round(cp["ms"], 2))
+        del keep, got
+        extra["learned_chem"] = mlp_info
+        log(f"learned chemistry vs plain: {mlp_info}")
 
     # Plain (per source, per level) schedule on a source subset: crossings/s of the paper's loop.
     nsrc = len(w.sources["ndot"])
     if args.plain_sample and args.schedule == "batched":
         idx = np.arange(0, nsrc, max(1, nsrc // args.plain_sample))[: args.plain_sample]
         sub = w.subset(idx)
-        lb = trace(g, sub.sources, "batched", **tune)
+        lb = trace(g, sub.sources, schedule, **tune)
         torch.cuda.synchronize()
         tp = time.perf_counter()
         lp = trace(g, sub.sources, "plain")
         torch.cuda.synchronize()
         tp = time.perf_counter() - tp
         tb = time.perf_counter()
-        lb = trace(g, sub.sources, "batched", **tune)
+        lb = trace(g, sub.sources, schedule, **tune)
         torch.cuda.synchronize()
         tb = time.perf_counter() - tb
         extra["plain_sample"] = {"sources": int(idx.size), "plain_crossings_per_s": round(lp["crossings"] / tp, 1),
@@ -155,7 +226,7 @@ def main():
                "sample": f"{idx.size} of {nsrc} sources (every {max(1, nsrc // args.cpu_sample)}th) on the full grid; "
                          f"{r['ledger']['crossings']} crossings in {tc:.1f}s including the FP64 opacity pass"}
         # the same sample on the GPU, checked against the oracle
-        gs = trace(g, sub.sources, "batched", **tune)
+        gs = trace(g, sub.sources, schedule, **tune)
         og = oracle.finalize(state, w.bins, r["J"])[0]
         gg = gamma.cpu().numpy()
         errs = []
@@ -183,13 +254,16 @@ def main():
         "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": names[args.config], "grid": list(w.shape), "sources": nsrc, "bins": nb,
-                   "schedule": args.schedule, "precision": args.precision, "chemistry": not args.no_chem,
+                   "schedule": schedule, "graph": bool(args.graph) and schedule != "plain",
+                   "precision": args.precision, "chemistry": args.chem,
                    "dt_myr": w.dt / W.MYR_S},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+    if net is not None:
+        net.close()
     ctx.close()
 
 

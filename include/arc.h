@@ -45,6 +45,7 @@ typedef int32_t arc_status;
 #define ARC_E_OVERFLOW (-5)    /* requested fixed-point unit cannot hold the field */
 #define ARC_E_QUEUE (-6)       /* ray-queue capacity exceeded */
 #define ARC_E_UNSUPPORTED (-7) /* valid but not implemented combination */
+#define ARC_E_MISMATCH (-8)    /* autotuner: two launch shapes gave different fields */
 
 typedef struct arc_ctx arc_ctx;
 
@@ -92,6 +93,9 @@ typedef struct {
 /* Work schedule. Both give bitwise-identical fixed-point fields for the same precision. */
 #define ARC_SCHED_PLAIN 0     /* per source, per HEALPix level launches (section 2.1 iii) */
 #define ARC_SCHED_BATCHED 1   /* every source in one persistent launch with a device queue */
+#define ARC_SCHED_BATCHED_TUNED 2 /* batched, with the launch shape the context's autotuner
+                                     chose for this grid (tuned on first use, see arc_autotune);
+                                     tune_* fields are ignored */
 
 typedef struct {
     int32_t level0;        /* HEALPix level of the root rays (section 2.1: typically 1) */
@@ -114,6 +118,10 @@ typedef struct {
                               (src << 32) | (level << 28) | pixel; NULL = off */
     int64_t tree_cap;      /* capacity of tree_out in entries */
     double u_j_override;   /* 0 = automatic fixed-point unit; > 0 forces this unit (tests) */
+    int32_t graph;         /* batched schedules: 1 = record the call's launches in HIP graphs
+                              once and replay them while every launch argument repeats
+                              (same grid, buffers, sources' fixed-point scales, shape);
+                              results are identical to 0 */
 } arc_trace_params;
 
 /* Rates out: device pointers, caller-owned, each [3][ncell] (HI, HeI, HeII). */
@@ -145,6 +153,29 @@ typedef struct {
 arc_status arc_trace(arc_ctx* ctx, const arc_grid* grid, const arc_sources* src,
                      const arc_freq_bins* bins, double dt, const arc_trace_params* params,
                      arc_rates* out, arc_ledger* ledger);
+
+/* Launch shape of the batched schedule. */
+typedef struct {
+    int32_t waves;         /* waves per workgroup of the persistent launch (1, 2, 4, 8) */
+    int32_t waves_per_cu;  /* resident waves per compute unit the grid is sized for */
+    int32_t refill;        /* refill a wave once this many lanes idle */
+    int32_t item_delta;    /* work-item level relative to the automatic choice */
+    double ms_best;        /* trace time of the chosen shape [ms] (tuning sources) */
+    double ms_default;     /* trace time of the default shape [ms] (tuning sources) */
+    int32_t candidates;    /* shapes timed */
+} arc_tune_result;
+
+/* Autotuner of the batched schedule (no paper counterpart: the paper traces one source
+ * at a time). Times launch shapes of the batched tracer on the given sources (pass a
+ * representative subset: every shape traces them all, twice) by coordinate descent over
+ * waves per workgroup and per CU, the refill threshold and the work-item level. Every
+ * shape's fixed-point field is checked against the first one's bit for bit (two 64-bit
+ * checksums); a difference returns ARC_E_MISMATCH. The best shape is cached in the context
+ * for this grid size, bin count, level range and precision, where ARC_SCHED_BATCHED_TUNED
+ * finds it. params->schedule and tune_* are ignored. The field and rates afterwards are
+ * those of the last shape timed. */
+arc_status arc_autotune(arc_ctx* ctx, const arc_grid* grid, const arc_sources* src, const arc_freq_bins* bins,
+                        double dt, const arc_trace_params* params, arc_rates* out, arc_tune_result* result);
 
 /* Copy the fixed-point field of the last arc_trace, [nbins][ncell] int64 in units of
  * ledger.u_j[b], into the device array `dst` (caller-owned, nbins * ncell entries). */

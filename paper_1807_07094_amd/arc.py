@@ -17,9 +17,9 @@ _lib = None
 
 ARC_OK = 0
 STATUS = {0: "ARC_OK", -1: "ARC_E_ARG", -2: "ARC_E_RANGE", -3: "ARC_E_NOMEM", -4: "ARC_E_DEVICE",
-          -5: "ARC_E_OVERFLOW", -6: "ARC_E_QUEUE", -7: "ARC_E_UNSUPPORTED"}
+          -5: "ARC_E_OVERFLOW", -6: "ARC_E_QUEUE", -7: "ARC_E_UNSUPPORTED", -8: "ARC_E_MISMATCH"}
 PREC = {"fp32_comp": 0, "fp32_plain": 1}
-SCHED = {"plain": 0, "batched": 1}
+SCHED = {"plain": 0, "batched": 1, "batched_tuned": 2}
 
 
 class ArcError(RuntimeError):
@@ -49,7 +49,13 @@ class TraceParams(C.Structure):
                 ("eps_term", C.c_double), ("precision", C.c_int32), ("schedule", C.c_int32),
                 ("stream", C.c_void_p), ("tune_waves", C.c_int32), ("tune_blocks", C.c_int32),
                 ("tune_refill", C.c_int32), ("tune_item_level", C.c_int32), ("tree_out", C.c_void_p),
-                ("tree_cap", C.c_int64), ("u_j_override", C.c_double)]
+                ("tree_cap", C.c_int64), ("u_j_override", C.c_double), ("graph", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("waves", C.c_int32), ("waves_per_cu", C.c_int32), ("refill", C.c_int32),
+                ("item_delta", C.c_int32), ("ms_best", C.c_double), ("ms_default", C.c_double),
+                ("candidates", C.c_int32)]
 
 
 class Rates(C.Structure):
@@ -104,6 +110,9 @@ def lib():
         L.arc_trace.restype = C.c_int32
         L.arc_trace.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Sources), C.POINTER(Bins), C.c_double,
                                 C.POINTER(TraceParams), C.POINTER(Rates), C.POINTER(Ledger)]
+        L.arc_autotune.restype = C.c_int32
+        L.arc_autotune.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Sources), C.POINTER(Bins), C.c_double,
+                                   C.POINTER(TraceParams), C.POINTER(Rates), C.POINTER(TuneResult)]
         L.arc_get_field.restype = C.c_int32
         L.arc_get_field.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.arc_healpix_dirs.restype = C.c_int32
@@ -189,10 +198,9 @@ class Context:
         if rc != ARC_OK:
             raise ArcError(rc, lib().arc_last_error(self._h).decode())
 
-    def trace(self, grid, sources: dict, bins: dict, dt: float, gamma, heat, level0=1, rays_per_cell=4.0,
-              max_level=-1, eps_term=1e-6, precision="fp32_comp", schedule="batched", stream=None, tree=None,
-              tune_waves=0, tune_blocks=0, tune_refill=0, tune_item_level=0, u_j_override=0.0) -> dict:
-        """arc_trace. gamma/heat: device float32 tensors of shape [3, nz, ny, nx]."""
+    @staticmethod
+    def _trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term, precision, schedule, stream,
+                    tree, tune_waves, tune_blocks, tune_refill, tune_item_level, u_j_override, graph):
         g = _grid(grid)
         pos = np.ascontiguousarray(sources["pos"], np.float64).reshape(-1, 3)
         ndot = np.ascontiguousarray(sources["ndot"], np.float64).reshape(-1)
@@ -206,7 +214,17 @@ class Context:
                         PREC[precision] if isinstance(precision, str) else int(precision),
                         SCHED[schedule] if isinstance(schedule, str) else int(schedule), _stream(stream),
                         int(tune_waves), int(tune_blocks), int(tune_refill), int(tune_item_level), _ptr(tree),
-                        int(tree.numel()) if tree is not None else 0, float(u_j_override))
+                        int(tree.numel()) if tree is not None else 0, float(u_j_override), int(bool(graph)))
+        # the host arrays must outlive the call: keep them with the structures
+        return g, s, b, p, (pos, ndot, frac, e, sig, thr)
+
+    def trace(self, grid, sources: dict, bins: dict, dt: float, gamma, heat, level0=1, rays_per_cell=4.0,
+              max_level=-1, eps_term=1e-6, precision="fp32_comp", schedule="batched", stream=None, tree=None,
+              tune_waves=0, tune_blocks=0, tune_refill=0, tune_item_level=0, u_j_override=0.0, graph=False) -> dict:
+        """arc_trace. gamma/heat: device float32 tensors of shape [3, nz, ny, nx]."""
+        g, s, b, p, _keep = self._trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term,
+                                             precision, schedule, stream, tree, tune_waves, tune_blocks, tune_refill,
+                                             tune_item_level, u_j_override, graph)
         r = Rates(_ptr(gamma), _ptr(heat))
         led = Ledger()
         self._check(lib().arc_trace(self._h, C.byref(g), C.byref(s), C.byref(b), float(dt), C.byref(p),
@@ -214,6 +232,18 @@ class Context:
         out = {k: getattr(led, k) for k, _ in Ledger._fields_ if k != "u_j"}
         out["u_j"] = list(led.u_j)
         return out
+
+    def autotune(self, grid, sources: dict, bins: dict, dt: float, gamma, heat, level0=1, rays_per_cell=4.0,
+                 max_level=-1, eps_term=1e-6, precision="fp32_comp", stream=None) -> dict:
+        """arc_autotune on these sources; the chosen shape is cached in the context for
+        schedule="batched_tuned"."""
+        g, s, b, p, _keep = self._trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term,
+                                             precision, "batched", stream, None, 0, 0, 0, 0, 0.0, False)
+        r = Rates(_ptr(gamma), _ptr(heat))
+        res = TuneResult()
+        self._check(lib().arc_autotune(self._h, C.byref(g), C.byref(s), C.byref(b), float(dt), C.byref(p),
+                                       C.byref(r), C.byref(res)))
+        return {k: getattr(res, k) for k, _ in TuneResult._fields_}
 
     def get_field(self, dst, stream=None):
         """arc_get_field into a device int64 tensor of nbins * ncell entries."""

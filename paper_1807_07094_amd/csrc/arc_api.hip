@@ -57,6 +57,17 @@ struct arc_ctx {
     int last_nb = 0, last_nbp = 0, last_nx = 0, last_ny = 0, last_nbx8 = 0, last_nby8 = 0;
     size_t last_ncell = 0;
     bool have_field = false;
+    // replayed launches of the batched schedule: [0] set-up, [1] the first levels, [2] the
+    // persistent trace, [3] the rates; valid while the launch arguments equal graph_key
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<unsigned char> graph_key;
+    unsigned long long* sums = nullptr;  // field checksums of the autotuner
+    struct Tuned {
+        int nx, ny, nz, nb, level0, lmax, precision;
+        arc_tune_result shape;
+    };
+    std::vector<Tuned> tuned;
 };
 
 namespace {
@@ -224,7 +235,8 @@ arc_status arc_create(int32_t device, arc_ctx** out)
               hipMalloc((void**)&c->acc, 8 * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&c->u32, 4 * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void**)&c->errflag, sizeof(int)) == hipSuccess &&
-              hipMalloc((void**)&c->chem_stats, 4 * sizeof(unsigned long long)) == hipSuccess;
+              hipMalloc((void**)&c->chem_stats, 4 * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void**)&c->sums, 2 * sizeof(unsigned long long)) == hipSuccess;
     for (int i = 0; i < 6 && ok; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
     if (!ok) {
         arc_destroy(c);
@@ -244,16 +256,49 @@ void arc_destroy(arc_ctx* c)
         if (p) (void)hipFree(p);
     for (int i = 0; i < 6; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    for (int i = 0; i < 4; ++i)
+        if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->sums) (void)hipFree(c->sums);
     delete c;
 }
 
 const char* arc_last_error(const arc_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const arc_freq_bins* b, double dt,
-                     const arc_trace_params* p, arc_rates* out, arc_ledger* ledger)
+}  // extern "C"
+
+namespace {
+
+// Everything one trace launches with. Zero-filled before use so that its bytes (padding
+// included) can serve as the key of the recorded graphs.
+struct TracePlan {
+    int nb, nbp, lmax;
+    size_t ncell;
+    int nbx8, nby8, nbz8;
+    double uj[kMaxBins];
+    double sum_ndot;
+    int nsrc;
+    double src_scale[kMaxBins];  // frac_b / (12 u_J,b)
+    OpacityArgs oa;
+    TraceArgs A;
+    FinalizeArgs fa;
+    int precision;
+    // batched schedule
+    int waves, blocks, refill, litem;
+    double n_roots;
+    size_t cap;
+    uint32_t spill_cap;
+    RayRec* rays0;
+    RayRec* rays1;
+    RayRec* spill;
+    uint32_t* u32;
+};
+
+// Validation, fixed-point units, buffers and launch arguments shared by both schedules.
+arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const arc_freq_bins* b, double dt,
+                      const arc_trace_params* p, const arc_rates* out, TracePlan& P)
 {
-    if (!c) return ARC_E_ARG;
-    c->err.clear();
+    std::memset(&P, 0, sizeof P);
     arc_status rc;
     if ((rc = check_grid(c, g)) != ARC_OK) return rc;
     if ((rc = check_bins(c, b)) != ARC_OK) return rc;
@@ -264,7 +309,8 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     if (!(p->rays_per_cell > 0) || !std::isfinite(p->rays_per_cell)) return fail(c, ARC_E_RANGE, "rays_per_cell must be > 0");
     if (!(p->eps_term >= 0 && p->eps_term < 1)) return fail(c, ARC_E_RANGE, "eps_term must be in [0,1)");
     if (p->precision != ARC_PREC_FP32_COMP && p->precision != ARC_PREC_FP32_PLAIN) return fail(c, ARC_E_ARG, "bad precision");
-    if (p->schedule != ARC_SCHED_PLAIN && p->schedule != ARC_SCHED_BATCHED) return fail(c, ARC_E_ARG, "bad schedule");
+    if (p->schedule != ARC_SCHED_PLAIN && p->schedule != ARC_SCHED_BATCHED && p->schedule != ARC_SCHED_BATCHED_TUNED)
+        return fail(c, ARC_E_ARG, "bad schedule");
     const int lmax = p->max_level < 0 ? auto_max_level(g->nx, g->ny, g->nz, p->rays_per_cell) : p->max_level;
     if (p->level0 < 0 || p->level0 > lmax) return fail(c, ARC_E_ARG, "level0 must be in [0, max_level]");
     if (lmax > 12) return fail(c, ARC_E_UNSUPPORTED, "max_level %d > 12 (pixel ids are 28-bit)", lmax);
@@ -279,26 +325,35 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     const int nbx8 = (g->nx + 7) / 8, nby8 = (g->ny + 7) / 8, nbz8 = (g->nz + 7) / 8;
     const size_t nblocked = (size_t)nbx8 * nby8 * nbz8 * 512;  // cells of the blocked layout
     if (nblocked > 2147483648ull) return fail(c, ARC_E_UNSUPPORTED, "blocked grid exceeds 2^31 cells");
+    P.nb = nb;
+    P.nbp = nbp;
+    P.lmax = lmax;
+    P.ncell = ncell;
+    P.nbx8 = nbx8;
+    P.nby8 = nby8;
+    P.nbz8 = nbz8;
+    P.nsrc = s->n;
+    P.precision = p->precision;
 
     // Fixed-point unit per bin. One source deposits at most sqrt(3) S_b into a cell
     // (the photon rate through any sphere is at most S_b and a cell is at most sqrt(3)
     // long), plus a remainder below eps_term S_b sqrt(3) / 0.01 on termination. The sum
     // over sources therefore stays below 2^62 units.
-    double uj[kMaxBins] = {1, 1, 1, 1};
-    double sum_ndot = 0;
-    for (int i = 0; i < s->n; ++i) sum_ndot += s->ndot[i];
+    for (int k = 0; k < kMaxBins; ++k) P.uj[k] = 1.0;
+    for (int i = 0; i < s->n; ++i) P.sum_ndot += s->ndot[i];
     for (int k = 0; k < nb; ++k) {
-        const double bound = (std::sqrt(3.0) + p->eps_term * std::sqrt(3.0) / (double)kDtauTermMin) * sum_ndot *
+        const double bound = (std::sqrt(3.0) + p->eps_term * std::sqrt(3.0) / (double)kDtauTermMin) * P.sum_ndot *
                              b->frac[k] * (1.0 + 1e-6);
         const double need = bound / 4611686018427387904.0;  // 2^62
         if (p->u_j_override > 0) {
             if (p->u_j_override < need)
                 return fail(c, ARC_E_OVERFLOW, "fixed-point unit %.6g too small for bin %d (needs >= %.6g)",
                             p->u_j_override, k, need);
-            uj[k] = p->u_j_override;
+            P.uj[k] = p->u_j_override;
         } else {
-            uj[k] = need > 0 ? need : 1.0;
+            P.uj[k] = need > 0 ? need : 1.0;
         }
+        P.src_scale[k] = b->frac[k] / (12.0 * P.uj[k]);
     }
 
     // Buffers.
@@ -321,12 +376,7 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     }
     if ((rc = ensure_dirs(c, lmax + 1, st)) != ARC_OK) return rc;
 
-    HIP_TRY(c, hipEventRecord(c->ev[0], st));
-    HIP_TRY(c, launch_zero_u64(c->counters, kNumCounters, st));
-    HIP_TRY(c, launch_zero_f64(c->acc, 8, st));
-    HIP_TRY(c, hipMemsetAsync(c->errflag, 0, sizeof(int), st));
-
-    OpacityArgs oa{};
+    OpacityArgs& oa = P.oa;
     oa.nb = nb;
     oa.nx = g->nx;
     oa.ny = g->ny;
@@ -348,17 +398,8 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     oa.J = c->J;
     oa.nbp = nbp;
     oa.errflag = c->errflag;
-    HIP_TRY(c, launch_opacity(oa, st));
 
-    if (s->n > 0) {
-        HIP_TRY(c, hipMemcpyAsync(c->src_pos, s->pos, s->n * 3 * sizeof(double), hipMemcpyHostToDevice, st));
-        HIP_TRY(c, hipMemcpyAsync(c->src_ndot, s->ndot, s->n * sizeof(double), hipMemcpyHostToDevice, st));
-        double f[kMaxBins];
-        for (int k = 0; k < nb; ++k) f[k] = b->frac[k] / (12.0 * uj[k]);
-        HIP_TRY(c, launch_sources(s->n, c->src_pos, c->src_ndot, f, nb, c->src, st));
-    }
-
-    TraceArgs A{};
+    TraceArgs& A = P.A;
     A.nx = g->nx;
     A.ny = g->ny;
     A.nz = g->nz;
@@ -382,111 +423,7 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     A.tree = (unsigned long long*)p->tree_out;
     A.tree_cap = p->tree_out ? p->tree_cap : 0;
 
-    HIP_TRY(c, hipEventRecord(c->ev[1], st));
-    c->timed_kernel = false;
-    const uint32_t npix0 = 12u << (2 * p->level0);
-    if (s->n > 0 && p->schedule == ARC_SCHED_PLAIN) {
-        // Section 2.1 iii: one source at a time, one HEALPix level per launch; the host
-        // reads back the number of children before launching the next level.
-        for (int si = 0; si < s->n; ++si) {
-            size_t n = npix0;
-            if (4 * n > c->rays_cap) {
-                size_t cap_bytes = c->rays_cap * sizeof(RayRec);
-                size_t cap2 = cap_bytes;
-                HIP_TRY(c, grow(&c->rays[0], &cap_bytes, 4 * n * sizeof(RayRec)));
-                HIP_TRY(c, grow(&c->rays[1], &cap2, 4 * n * sizeof(RayRec)));
-                c->rays_cap = 4 * n;
-            }
-            HIP_TRY(c, launch_seed_roots((uint32_t)si, 1, p->level0, c->rays[0], st));
-            int cur = 0;
-            while (n > 0) {
-                const size_t need = 4 * n;
-                if (need > c->rays_cap) {
-                    // grow both arrays, keeping the current level's rays
-                    RayRec* a = nullptr;
-                    RayRec* bb = nullptr;
-                    HIP_TRY(c, hipStreamSynchronize(st));
-                    HIP_TRY(c, hipMalloc((void**)&a, need * sizeof(RayRec)));
-                    HIP_TRY(c, hipMalloc((void**)&bb, need * sizeof(RayRec)));
-                    HIP_TRY(c, hipMemcpyAsync(a, c->rays[cur], n * sizeof(RayRec), hipMemcpyDeviceToDevice, st));
-                    HIP_TRY(c, hipStreamSynchronize(st));
-                    HIP_TRY(c, hipFree(c->rays[0]));
-                    HIP_TRY(c, hipFree(c->rays[1]));
-                    c->rays[0] = a;
-                    c->rays[1] = bb;
-                    cur = 0;
-                    c->rays_cap = need;
-                }
-                HIP_TRY(c, hipMemsetAsync(c->u32, 0, sizeof(uint32_t), st));
-                HIP_TRY(c, launch_trace_rays(A, p->precision, c->rays[cur], nullptr, (uint32_t)n, c->rays[1 - cur],
-                                             c->u32, (uint32_t)c->rays_cap, st));
-                uint32_t nn = 0;
-                HIP_TRY(c, hipMemcpyAsync(&nn, c->u32, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-                HIP_TRY(c, hipStreamSynchronize(st));
-                n = nn;
-                cur = 1 - cur;
-            }
-        }
-    } else if (s->n > 0) {
-        // Levels level0 .. item_level-1 are traced level by level for every source at once
-        // (the ray count stays on the device); the rays of item_level are then the work
-        // items of one persistent launch that traces each subtree depth first.
-        int waves = p->tune_waves > 0 ? p->tune_waves : 4;
-        if (waves != 1 && waves != 2 && waves != 4 && waves != 8)
-            return fail(c, ARC_E_ARG, "tune_waves must be 1, 2, 4 or 8");
-        const int blocks = p->tune_blocks > 0 ? p->tune_blocks : c->cus * (16 / waves);
-        const int refill = p->tune_refill > 0 ? std::min(64, p->tune_refill) : 8;
-        const double n_roots = (double)s->n * npix0;
-        int litem = p->level0;
-        if (p->tune_item_level > 0) {
-            litem = std::max(p->level0, std::min(lmax, (int)p->tune_item_level));
-        } else {
-            const double want = 16.0 * blocks * waves;
-            while (litem < lmax && n_roots * std::ldexp(1.0, 2 * (litem - p->level0)) < want &&
-                   n_roots * std::ldexp(1.0, 2 * (litem + 1 - p->level0)) <= (double)(1u << 26))
-                ++litem;
-        }
-        const double max_items = n_roots * std::ldexp(1.0, 2 * (litem - p->level0));
-        if (max_items > (double)0xFFFFFFF0u) return fail(c, ARC_E_UNSUPPORTED, "too many work items");
-        const size_t cap = (size_t)max_items;
-        if (cap > c->rays_cap) {
-            size_t cap_bytes = c->rays_cap * sizeof(RayRec);
-            size_t cap2 = cap_bytes;
-            HIP_TRY(c, grow(&c->rays[0], &cap_bytes, cap * sizeof(RayRec)));
-            HIP_TRY(c, grow(&c->rays[1], &cap2, cap * sizeof(RayRec)));
-            c->rays_cap = cap;
-        }
-        const uint32_t spill_cap = 4096;
-        const size_t spill_need = (size_t)blocks * waves * spill_cap;
-        if (spill_need > c->spill_entries) {
-            size_t cap_bytes = c->spill_entries * sizeof(RayRec);
-            HIP_TRY(c, grow(&c->spill, &cap_bytes, spill_need * sizeof(RayRec)));
-            c->spill_entries = spill_need;
-        }
-        HIP_TRY(c, launch_seed_roots(0, (uint32_t)s->n, p->level0, c->rays[0], st));
-        int cur = 0;
-        uint32_t* cnt = c->u32 + 2;  // [2], [3]: ray counts of consecutive levels
-        HIP_TRY(c, launch_set_u32(cnt, (uint32_t)n_roots, st));
-        size_t bound = (size_t)n_roots;
-        for (int l = p->level0; l < litem; ++l) {
-            uint32_t* cin = cnt + ((l - p->level0) & 1);
-            uint32_t* cout = cnt + ((l - p->level0 + 1) & 1);
-            HIP_TRY(c, launch_set_u32(cout, 0u, st));
-            HIP_TRY(c, launch_trace_rays(A, p->precision, c->rays[cur], cin, (uint32_t)bound, c->rays[1 - cur], cout,
-                                         (uint32_t)cap, st));
-            bound *= 4;
-            cur = 1 - cur;
-        }
-        HIP_TRY(c, launch_set_u32(c->u32 + 1, 0u, st));
-        HIP_TRY(c, hipEventRecord(c->ev[4], st));
-        c->timed_kernel = true;
-        HIP_TRY(c, launch_trace_persistent(A, p->precision, c->rays[cur], cnt + ((litem - p->level0) & 1), c->u32 + 1,
-                                           c->spill, spill_cap, blocks, waves, refill, st));
-        HIP_TRY(c, hipEventRecord(c->ev[5], st));
-    }
-    HIP_TRY(c, hipEventRecord(c->ev[2], st));
-
-    FinalizeArgs fa{};
+    FinalizeArgs& fa = P.fa;
     fa.nb = nb;
     fa.nbp = nbp;
     fa.nx = g->nx;
@@ -496,11 +433,11 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     fa.ncell = (uint32_t)ncell;
     const double L2 = g->cell_cm * g->cell_cm;
     for (int k = 0; k < nb; ++k) {
-        fa.uj[k] = uj[k];
+        fa.uj[k] = P.uj[k];
         for (int sp = 0; sp < 3; ++sp) {
-            fa.gam[k][sp] = uj[k] * b->sigma[3 * k + sp] / L2;
+            fa.gam[k][sp] = P.uj[k] * b->sigma[3 * k + sp] / L2;
             const double excess = b->e_erg[k] - b->e_thr[sp];
-            fa.hea[k][sp] = excess > 0 ? uj[k] * b->sigma[3 * k + sp] * excess / L2 : 0.0;
+            fa.hea[k][sp] = excess > 0 ? P.uj[k] * b->sigma[3 * k + sp] * excess / L2 : 0.0;
         }
     }
     fa.J = c->J;
@@ -509,8 +446,241 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     fa.gamma = out->gamma;
     fa.heat = out->heat;
     fa.absorbed = c->acc + 4;
-    HIP_TRY(c, launch_finalize(fa, st));
-    HIP_TRY(c, hipEventRecord(c->ev[3], st));
+    return ARC_OK;
+}
+
+// Launch shape of the batched schedule and the buffers it needs. item_delta moves the
+// work-item level from the automatic choice (the first level with >= 16 items per wave).
+arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int refill, int item_level, int item_delta)
+{
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(c, ARC_E_ARG, "tune_waves must be 1, 2, 4 or 8");
+    if (blocks < 1) return fail(c, ARC_E_ARG, "tune_blocks must be >= 1");
+    const int level0 = P.A.level0, lmax = P.lmax;
+    const uint32_t npix0 = 12u << (2 * level0);
+    const double n_roots = (double)P.nsrc * npix0;
+    int litem = level0;
+    if (item_level > 0) {
+        litem = std::max(level0, std::min(lmax, item_level));
+    } else {
+        const double want = 16.0 * blocks * waves;
+        while (litem < lmax && n_roots * std::ldexp(1.0, 2 * (litem - level0)) < want &&
+               n_roots * std::ldexp(1.0, 2 * (litem + 1 - level0)) <= (double)(1u << 26))
+            ++litem;
+        litem = std::max(level0, std::min(lmax, litem + item_delta));
+        while (litem > level0 && n_roots * std::ldexp(1.0, 2 * (litem - level0)) > (double)(1u << 28)) --litem;
+    }
+    const double max_items = n_roots * std::ldexp(1.0, 2 * (litem - level0));
+    if (max_items > (double)0xFFFFFFF0u) return fail(c, ARC_E_UNSUPPORTED, "too many work items");
+    const size_t cap = std::max<size_t>(1, (size_t)max_items);
+    if (cap > c->rays_cap) {
+        size_t cap_bytes = c->rays_cap * sizeof(RayRec);
+        size_t cap2 = cap_bytes;
+        HIP_TRY(c, grow(&c->rays[0], &cap_bytes, cap * sizeof(RayRec)));
+        HIP_TRY(c, grow(&c->rays[1], &cap2, cap * sizeof(RayRec)));
+        c->rays_cap = cap;
+    }
+    const uint32_t spill_cap = 4096;
+    const size_t spill_need = (size_t)blocks * waves * spill_cap;
+    if (spill_need > c->spill_entries) {
+        size_t cap_bytes = c->spill_entries * sizeof(RayRec);
+        HIP_TRY(c, grow(&c->spill, &cap_bytes, spill_need * sizeof(RayRec)));
+        c->spill_entries = spill_need;
+    }
+    P.waves = waves;
+    P.blocks = blocks;
+    P.refill = std::max(1, std::min(64, refill));
+    P.litem = litem;
+    P.n_roots = n_roots;
+    P.cap = cap;
+    P.spill_cap = spill_cap;
+    P.rays0 = c->rays[0];
+    P.rays1 = c->rays[1];
+    P.spill = c->spill;
+    P.u32 = c->u32;
+    return ARC_OK;
+}
+
+// Stage 0: counters, opacity (section 2.2 cross sections times densities) and the
+// source table.
+hipError_t enqueue_common(arc_ctx* c, const TracePlan& P, hipStream_t st)
+{
+    hipError_t e;
+    if ((e = launch_zero_u64(c->counters, kNumCounters, st)) != hipSuccess) return e;
+    if ((e = launch_zero_f64(c->acc, 8, st)) != hipSuccess) return e;
+    if ((e = launch_set_u32((uint32_t*)c->errflag, 0u, st)) != hipSuccess) return e;
+    if ((e = launch_opacity(P.oa, st)) != hipSuccess) return e;
+    if (P.nsrc > 0 && (e = launch_sources(P.nsrc, c->src_pos, c->src_ndot, P.src_scale, P.nb, c->src, st)) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+// Stage 1 (batched): the root rays of every source and the levels traced level by level
+// before the persistent launch.
+hipError_t enqueue_levels(const TracePlan& P, hipStream_t st)
+{
+    hipError_t e;
+    if (P.nsrc == 0) return hipSuccess;
+    if ((e = launch_seed_roots(0, (uint32_t)P.nsrc, P.A.level0, P.rays0, st)) != hipSuccess) return e;
+    uint32_t* cnt = P.u32 + 2;  // [2], [3]: ray counts of consecutive levels
+    if ((e = launch_set_u32(cnt, (uint32_t)P.n_roots, st)) != hipSuccess) return e;
+    size_t bound = (size_t)P.n_roots;
+    int cur = 0;
+    RayRec* r[2] = {P.rays0, P.rays1};
+    for (int l = P.A.level0; l < P.litem; ++l) {
+        uint32_t* cin = cnt + ((l - P.A.level0) & 1);
+        uint32_t* cout = cnt + ((l - P.A.level0 + 1) & 1);
+        if ((e = launch_set_u32(cout, 0u, st)) != hipSuccess) return e;
+        if ((e = launch_trace_rays(P.A, P.precision, r[cur], cin, (uint32_t)bound, r[1 - cur], cout, (uint32_t)P.cap,
+                                   st)) != hipSuccess)
+            return e;
+        bound *= 4;
+        cur = 1 - cur;
+    }
+    return launch_set_u32(P.u32 + 1, 0u, st);
+}
+
+// Stage 2: the persistent launch over the work items of level litem.
+hipError_t enqueue_persistent(const TracePlan& P, hipStream_t st)
+{
+    if (P.nsrc == 0) return hipSuccess;
+    const int cur = (P.litem - P.A.level0) & 1;
+    return launch_trace_persistent(P.A, P.precision, cur ? P.rays1 : P.rays0, P.u32 + 2 + cur, P.u32 + 1, P.spill,
+                                   P.spill_cap, P.blocks, P.waves, P.refill, st);
+}
+
+// Stage 3: rates (eq:ion per absorber, section 2.8 heating) and the absorbed ledger.
+hipError_t enqueue_rates(const TracePlan& P, hipStream_t st) { return launch_finalize(P.fa, st); }
+
+// Section 2.1 iii: one source at a time, one HEALPix level per launch; the host reads
+// back the number of children before launching the next level.
+arc_status run_plain(arc_ctx* c, const TracePlan& P, hipStream_t st)
+{
+    const uint32_t npix0 = 12u << (2 * P.A.level0);
+    for (int si = 0; si < P.nsrc; ++si) {
+        size_t n = npix0;
+        if (4 * n > c->rays_cap) {
+            size_t cap_bytes = c->rays_cap * sizeof(RayRec);
+            size_t cap2 = cap_bytes;
+            HIP_TRY(c, grow(&c->rays[0], &cap_bytes, 4 * n * sizeof(RayRec)));
+            HIP_TRY(c, grow(&c->rays[1], &cap2, 4 * n * sizeof(RayRec)));
+            c->rays_cap = 4 * n;
+        }
+        HIP_TRY(c, launch_seed_roots((uint32_t)si, 1, P.A.level0, c->rays[0], st));
+        int cur = 0;
+        while (n > 0) {
+            const size_t need = 4 * n;
+            if (need > c->rays_cap) {
+                // grow both arrays, keeping the current level's rays
+                RayRec* a = nullptr;
+                RayRec* bb = nullptr;
+                HIP_TRY(c, hipStreamSynchronize(st));
+                HIP_TRY(c, hipMalloc((void**)&a, need * sizeof(RayRec)));
+                HIP_TRY(c, hipMalloc((void**)&bb, need * sizeof(RayRec)));
+                HIP_TRY(c, hipMemcpyAsync(a, c->rays[cur], n * sizeof(RayRec), hipMemcpyDeviceToDevice, st));
+                HIP_TRY(c, hipStreamSynchronize(st));
+                HIP_TRY(c, hipFree(c->rays[0]));
+                HIP_TRY(c, hipFree(c->rays[1]));
+                c->rays[0] = a;
+                c->rays[1] = bb;
+                cur = 0;
+                c->rays_cap = need;
+            }
+            HIP_TRY(c, launch_set_u32(c->u32, 0u, st));
+            HIP_TRY(c, launch_trace_rays(P.A, P.precision, c->rays[cur], nullptr, (uint32_t)n, c->rays[1 - cur], c->u32,
+                                         (uint32_t)c->rays_cap, st));
+            uint32_t nn = 0;
+            HIP_TRY(c, hipMemcpyAsync(&nn, c->u32, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            HIP_TRY(c, hipStreamSynchronize(st));
+            n = nn;
+            cur = 1 - cur;
+        }
+    }
+    return ARC_OK;
+}
+
+// Records the four stages of the batched schedule as graphs (on the context's own
+// capture stream) unless the recorded ones were made with the same arguments.
+arc_status ensure_graphs(arc_ctx* c, const TracePlan& P)
+{
+    const unsigned char* key = reinterpret_cast<const unsigned char*>(&P);
+    if (c->gexec[0] && c->graph_key.size() == sizeof P && std::memcmp(c->graph_key.data(), key, sizeof P) == 0)
+        return ARC_OK;
+    for (int i = 0; i < 4; ++i)
+        if (c->gexec[i]) {
+            HIP_TRY(c, hipGraphExecDestroy(c->gexec[i]));
+            c->gexec[i] = nullptr;
+        }
+    c->graph_key.clear();
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    for (int i = 0; i < 4; ++i) {
+        HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipStream_t cs = c->cap_stream;
+        const hipError_t e = i == 0   ? enqueue_common(c, P, cs)
+                             : i == 1 ? enqueue_levels(P, cs)
+                             : i == 2 ? enqueue_persistent(P, cs)
+                                      : enqueue_rates(P, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(c, ARC_E_DEVICE, "graph capture of stage %d: %s", i,
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        const hipError_t e3 = hipGraphInstantiate(&c->gexec[i], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+            c->gexec[i] = nullptr;
+            return fail(c, ARC_E_DEVICE, "graph instantiation of stage %d: %s", i, hipGetErrorString(e3));
+        }
+    }
+    c->graph_key.assign(key, key + sizeof P);
+    return ARC_OK;
+}
+
+// One whole trace with a planned shape: uploads, the stages (eagerly or as graphs),
+// event timing, and the read-back of counters, ledger and error flags.
+arc_status run_trace(arc_ctx* c, const TracePlan& P, const arc_sources* s, double dt, int schedule, bool graph,
+                     hipStream_t st, arc_ledger* ledger)
+{
+    if (s->n > 0) {
+        HIP_TRY(c, hipMemcpyAsync(c->src_pos, s->pos, s->n * 3 * sizeof(double), hipMemcpyHostToDevice, st));
+        HIP_TRY(c, hipMemcpyAsync(c->src_ndot, s->ndot, s->n * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    const bool batched = schedule != ARC_SCHED_PLAIN;
+    c->timed_kernel = false;
+    if (batched && graph) {
+        arc_status rc = ensure_graphs(c, P);
+        if (rc != ARC_OK) return rc;
+        HIP_TRY(c, hipEventRecord(c->ev[0], st));
+        HIP_TRY(c, hipGraphLaunch(c->gexec[0], st));
+        HIP_TRY(c, hipEventRecord(c->ev[1], st));
+        HIP_TRY(c, hipGraphLaunch(c->gexec[1], st));
+        HIP_TRY(c, hipEventRecord(c->ev[4], st));
+        HIP_TRY(c, hipGraphLaunch(c->gexec[2], st));
+        HIP_TRY(c, hipEventRecord(c->ev[5], st));
+        HIP_TRY(c, hipEventRecord(c->ev[2], st));
+        HIP_TRY(c, hipGraphLaunch(c->gexec[3], st));
+        HIP_TRY(c, hipEventRecord(c->ev[3], st));
+        c->timed_kernel = P.nsrc > 0;
+    } else {
+        HIP_TRY(c, hipEventRecord(c->ev[0], st));
+        HIP_TRY(c, enqueue_common(c, P, st));
+        // the first levels of the batched schedule belong to the trace time
+        HIP_TRY(c, hipEventRecord(c->ev[1], st));
+        if (batched) {
+            HIP_TRY(c, enqueue_levels(P, st));
+            HIP_TRY(c, hipEventRecord(c->ev[4], st));
+            HIP_TRY(c, enqueue_persistent(P, st));
+            HIP_TRY(c, hipEventRecord(c->ev[5], st));
+            c->timed_kernel = P.nsrc > 0;
+        } else {
+            arc_status rc = run_plain(c, P, st);
+            if (rc != ARC_OK) return rc;
+        }
+        HIP_TRY(c, hipEventRecord(c->ev[2], st));
+        HIP_TRY(c, enqueue_rates(P, st));
+        HIP_TRY(c, hipEventRecord(c->ev[3], st));
+    }
 
     unsigned long long cnt[kNumCounters];
     double acc[8];
@@ -520,21 +690,21 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     HIP_TRY(c, hipMemcpyAsync(&errflag, c->errflag, sizeof errflag, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
 
-    c->last_nb = nb;
-    c->last_nbp = nbp;
-    c->last_ncell = ncell;
-    c->last_nx = g->nx;
-    c->last_ny = g->ny;
-    c->last_nbx8 = nbx8;
-    c->last_nby8 = nby8;
+    c->last_nb = P.nb;
+    c->last_nbp = P.nbp;
+    c->last_ncell = P.ncell;
+    c->last_nx = P.A.nx;
+    c->last_ny = P.A.ny;
+    c->last_nbx8 = P.nbx8;
+    c->last_nby8 = P.nby8;
     c->have_field = true;
     if (errflag) return fail(c, ARC_E_RANGE, "grid values out of range (n_h <= 0, fraction outside [0,1] or non-finite)");
     if (cnt[kQueueOverflow]) return fail(c, ARC_E_QUEUE, "ray queue capacity exceeded (%llu rays dropped)", cnt[kQueueOverflow]);
     if (ledger) {
         std::memset(ledger, 0, sizeof *ledger);
-        ledger->emitted = sum_ndot * dt;
+        ledger->emitted = P.sum_ndot * dt;
         double esc = 0;
-        for (int k = 0; k < nb; ++k) esc += acc[k] * uj[k];
+        for (int k = 0; k < P.nb; ++k) esc += acc[k] * P.uj[k];
         ledger->escaped = esc * dt;
         ledger->absorbed = acc[4] * dt;
         ledger->crossings = cnt[kCrossings];
@@ -544,7 +714,7 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
         ledger->escaped_rays = cnt[kEscapedRays];
         ledger->spills = cnt[kSpills];
         ledger->tree_count = (int64_t)cnt[kTreeCount];
-        for (int k = 0; k < kMaxBins; ++k) ledger->u_j[k] = k < nb ? uj[k] : 0.0;
+        for (int k = 0; k < kMaxBins; ++k) ledger->u_j[k] = k < P.nb ? P.uj[k] : 0.0;
         float ms = 0;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
         ledger->ms_trace = ms;
@@ -558,6 +728,181 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     }
     return ARC_OK;
 }
+
+const arc_tune_result* find_tuned(const arc_ctx* c, const arc_grid* g, const TracePlan& P)
+{
+    for (const auto& t : c->tuned)
+        if (t.nx == g->nx && t.ny == g->ny && t.nz == g->nz && t.nb == P.nb && t.level0 == P.A.level0 &&
+            t.lmax == P.lmax && t.precision == P.precision)
+            return &t.shape;
+    return nullptr;
+}
+
+arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, const arc_freq_bins* b, double dt,
+                         const arc_trace_params* p, const arc_rates* out, arc_tune_result* res);
+
+}  // namespace
+
+extern "C" {
+
+arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const arc_freq_bins* b, double dt,
+                     const arc_trace_params* p, arc_rates* out, arc_ledger* ledger)
+{
+    if (!c) return ARC_E_ARG;
+    c->err.clear();
+    TracePlan P;
+    arc_status rc = plan_trace(c, g, s, b, dt, p, out, P);
+    if (rc != ARC_OK) return rc;
+    hipStream_t st = (hipStream_t)p->stream;
+    if (p->schedule == ARC_SCHED_BATCHED) {
+        const int waves = p->tune_waves > 0 ? p->tune_waves : 4;
+        const int blocks = p->tune_blocks > 0 ? p->tune_blocks : std::max(1, c->cus * (16 / std::max(1, waves)));
+        const int refill = p->tune_refill > 0 ? p->tune_refill : 8;
+        if ((rc = shape_batched(c, P, waves, blocks, refill, p->tune_item_level, 0)) != ARC_OK) return rc;
+    } else if (p->schedule == ARC_SCHED_BATCHED_TUNED) {
+        const arc_tune_result* t = find_tuned(c, g, P);
+        arc_tune_result fresh;
+        if (!t) {
+            // tune on an evenly spaced subset of at most 256 sources
+            const int step = std::max(1, (s->n + 255) / 256);
+            std::vector<double> pos, nd;
+            for (int i = 0; i < s->n; i += step) {
+                pos.insert(pos.end(), s->pos + 3 * i, s->pos + 3 * i + 3);
+                nd.push_back(s->ndot[i]);
+            }
+            const arc_sources sub{(int32_t)nd.size(), pos.data(), nd.data()};
+            if ((rc = autotune_impl(c, g, &sub, b, dt, p, out, &fresh)) != ARC_OK) return rc;
+            t = &fresh;
+            // the tuning runs changed the plan's buffers: plan again for all sources
+            if ((rc = plan_trace(c, g, s, b, dt, p, out, P)) != ARC_OK) return rc;
+        }
+        const int blocks = std::max(1, c->cus * t->waves_per_cu / t->waves);
+        if ((rc = shape_batched(c, P, t->waves, blocks, t->refill, 0, t->item_delta)) != ARC_OK) return rc;
+    }
+    return run_trace(c, P, s, dt, p->schedule, p->graph != 0, st, ledger);
+}
+
+arc_status arc_autotune(arc_ctx* c, const arc_grid* g, const arc_sources* s, const arc_freq_bins* b, double dt,
+                        const arc_trace_params* p, arc_rates* out, arc_tune_result* res)
+{
+    if (!c) return ARC_E_ARG;
+    c->err.clear();
+    arc_tune_result r;
+    arc_status rc = autotune_impl(c, g, s, b, dt, p, out, &r);
+    if (rc == ARC_OK && res) *res = r;
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, const arc_freq_bins* b, double dt,
+                         const arc_trace_params* p, const arc_rates* out, arc_tune_result* res)
+{
+    if (!p) return fail(c, ARC_E_ARG, "null params");
+    arc_trace_params q = *p;
+    q.schedule = ARC_SCHED_BATCHED;
+    q.tree_out = nullptr;
+    q.tree_cap = 0;
+    TracePlan P;
+    arc_status rc = plan_trace(c, g, s, b, dt, &q, out, P);
+    if (rc != ARC_OK) return rc;
+    if (s->n == 0) return fail(c, ARC_E_ARG, "autotuning needs at least one source");
+    hipStream_t st = (hipStream_t)q.stream;
+    unsigned long long ref[2] = {0, 0};
+    bool have_ref = false;
+    int ncand = 0;
+    // time one shape twice; check its field against the first shape's
+    auto time_shape = [&](const arc_tune_result& t, double* ms_out) -> arc_status {
+        const int blocks = std::max(1, c->cus * t.waves_per_cu / t.waves);
+        arc_status r2 = shape_batched(c, P, t.waves, blocks, t.refill, 0, t.item_delta);
+        if (r2 != ARC_OK) return r2;
+        double best = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {
+            arc_ledger led;
+            if ((r2 = run_trace(c, P, s, dt, ARC_SCHED_BATCHED, false, st, &led)) != ARC_OK) return r2;
+            best = std::min(best, led.ms_trace);
+        }
+        HIP_TRY(c, launch_zero_u64(c->sums, 2, st));
+        HIP_TRY(c, launch_field_checksum(c->J, (size_t)P.nbx8 * P.nby8 * P.nbz8 * 512 * P.nbp, c->sums, st));
+        unsigned long long h[2];
+        HIP_TRY(c, hipMemcpyAsync(h, c->sums, sizeof h, hipMemcpyDeviceToHost, st));
+        HIP_TRY(c, hipStreamSynchronize(st));
+        if (!have_ref) {
+            ref[0] = h[0];
+            ref[1] = h[1];
+            have_ref = true;
+        } else if (h[0] != ref[0] || h[1] != ref[1]) {
+            return fail(c, ARC_E_MISMATCH,
+                        "launch shape (waves %d, waves/CU %d, refill %d, item delta %d) changed the field",
+                        t.waves, t.waves_per_cu, t.refill, t.item_delta);
+        }
+        ++ncand;
+        *ms_out = best;
+        return ARC_OK;
+    };
+    arc_tune_result best{};
+    best.waves = 4;
+    best.waves_per_cu = 16;
+    best.refill = 8;
+    best.item_delta = 0;
+    double ms_best;
+    if ((rc = time_shape(best, &ms_best)) != ARC_OK) return rc;
+    const double ms_default = ms_best;
+    auto consider = [&](arc_tune_result t) -> arc_status {
+        double ms;
+        arc_status r2 = time_shape(t, &ms);
+        if (r2 != ARC_OK) return r2;
+        if (ms < ms_best) {
+            ms_best = ms;
+            best = t;
+        }
+        return ARC_OK;
+    };
+    // (1) waves per workgroup and resident waves per CU
+    const arc_tune_result base1 = best;
+    for (int wv : {2, 4, 8})
+        for (int wpc : {8, 12, 16}) {
+            if (wv == base1.waves && wpc == base1.waves_per_cu) continue;
+            arc_tune_result t = base1;
+            t.waves = wv;
+            t.waves_per_cu = wpc;
+            if ((rc = consider(t)) != ARC_OK) return rc;
+        }
+    // (2) refill threshold
+    const arc_tune_result base2 = best;
+    for (int rf : {4, 16, 32}) {
+        if (rf == base2.refill) continue;
+        arc_tune_result t = base2;
+        t.refill = rf;
+        if ((rc = consider(t)) != ARC_OK) return rc;
+    }
+    // (3) work-item level
+    const arc_tune_result base3 = best;
+    for (int d : {-1, 1, 2}) {
+        arc_tune_result t = base3;
+        t.item_delta = d;
+        if ((rc = consider(t)) != ARC_OK) return rc;
+    }
+    best.ms_best = ms_best;
+    best.ms_default = ms_default;
+    best.candidates = ncand;
+    bool stored = false;
+    for (auto& t : c->tuned)
+        if (t.nx == g->nx && t.ny == g->ny && t.nz == g->nz && t.nb == P.nb && t.level0 == P.A.level0 &&
+            t.lmax == P.lmax && t.precision == P.precision) {
+            t.shape = best;
+            stored = true;
+        }
+    if (!stored) c->tuned.push_back({g->nx, g->ny, g->nz, P.nb, P.A.level0, P.lmax, P.precision, best});
+    *res = best;
+    return ARC_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 arc_status arc_get_field(arc_ctx* c, int64_t* dst, int64_t count, void* stream)
 {

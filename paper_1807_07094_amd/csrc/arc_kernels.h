@@ -53,6 +53,8 @@ struct ChemArgs {
 hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
+// out[0] = sum J[i], out[1] = sum J[i] (2i + 1), both mod 2^64; out must be zeroed first.
+hipError_t launch_field_checksum(const unsigned long long* J, size_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_opacity(const OpacityArgs& a, hipStream_t s);
 hipError_t launch_healpix(int level, float4* out, hipStream_t s);
 hipError_t launch_sources(int n, const double* pos, const double* ndot, const double* frac_over_12uj, int nb,

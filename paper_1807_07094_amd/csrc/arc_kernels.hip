@@ -52,6 +52,29 @@ hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// Two 64-bit sums of the fixed-point field, sum J[i] and sum J[i] (2 i + 1), modulo 2^64:
+// equal fields give equal sums bit for bit (integer adds in any order).
+__global__ __launch_bounds__(256) void k_field_checksum(const unsigned long long* J, size_t n, unsigned long long* out)
+{
+    unsigned long long s0 = 0, s1 = 0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        s0 += J[i];
+        s1 += J[i] * (2ull * i + 1ull);
+    }
+    s0 = wave_sum_u64(s0);
+    s1 = wave_sum_u64(s1);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(out, s0);
+        atomicAdd(out + 1, s1);
+    }
+}
+
+hipError_t launch_field_checksum(const unsigned long long* J, size_t n, unsigned long long* out, hipStream_t s)
+{
+    k_field_checksum<<<grid_for(n, 256, 4096), 256, 0, s>>>(J, n, out);
+    return hipGetLastError();
+}
+
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s)
@@ -271,6 +294,9 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
                                                     RayRec* __restrict__ out, uint32_t* n_out, uint32_t out_cap)
 {
     const uint32_t n_in = n_in_dev ? *n_in_dev : n_in_host;
+    __shared__ DepLds<NB> dscr[4];
+    Depositor<NB> dep{A, dscr + (threadIdx.x >> 6)};
+    dep.init();
     LaneStats st;
     st.clear();
     const int lane = threadIdx.x & 63;
@@ -288,8 +314,7 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
         }
         // a few crossings per lane per pass; the wave deposits each crossing together
         while (__any(act)) {
-            const int e = trace_pass<NB, PREC, kSegAhead>(A, ray, act, st,
-                                                          [&](const Dep<NB>& d) { deposit_wave<NB>(A, d); });
+            const int e = trace_pass<NB, PREC, kSegAhead>(A, ray, act, st, dep);
             if (act && e != kContinue) {
                 ev = e;
                 act = false;
@@ -361,11 +386,14 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
 {
     using SRec = StackRec<NB>;
     __shared__ SRec lds[WPB * kStackCap];
+    __shared__ DepLds<NB> dscr[WPB];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint64_t lt = __lanemask_lt();
     const uint32_t n_items = *n_items_dev;
     SRec* stk = lds + wid * kStackCap;
+    Depositor<NB> dep{A, dscr + wid};
+    dep.init();
     // the spill area is sized in full records; compact records fit in it
     SRec* spill = reinterpret_cast<SRec*>(spill_all + (size_t)(blockIdx.x * WPB + wid) * spill_cap);
     int base = 0;          // ring start (oldest entry), wave-uniform
@@ -434,8 +462,7 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
             if (top == 0 && nspill == 0 && qdone) break;
             continue;
         }
-        const int ev = trace_pass<NB, PREC, kSegAhead>(A, ray, has, st,
-                                                       [&](const Dep<NB>& d) { deposit_wave<NB>(A, d); });
+        const int ev = trace_pass<NB, PREC, kSegAhead>(A, ray, has, st, dep);
         const uint64_t sp = __ballot(ev == kSplit);
         if (sp) {
             const int need = 3 * __popcll(sp);

@@ -11,7 +11,7 @@ namespace mlp {
 
 constexpr int kIn = 5;       // log10 n_H, x_HI, log10 T, log10 Gamma_HI, log10 dt
 constexpr int kHid = 64;
-constexpr int kOut = 2;      // x_HI' (through a sigmoid), log10 T' (standardised)
+constexpr int kOut = 2;      // standardised changes of x_HI and of log10 T over dt
 constexpr int kK1 = 32;      // layer-1 depth padded to one MFMA step
 constexpr int kOutP = 16;    // layer-3 width padded to one MFMA tile
 constexpr int kGate = 8;     // gate bins per input feature
@@ -31,7 +31,7 @@ constexpr int kNParams = kB3 + kOut;
 struct Model {
     float in_mu[kIn], in_sd[kIn];   // feature standardisation
     float lo[kIn], hi[kIn];         // training range of each feature (gate)
-    float t_mu, t_sd;               // standardisation of log10 T'
+    float out_mu[kOut], out_sd[kOut];  // standardisation of the outputs (x_HI' - x_HI, log10 T'/T)
     float b1[kHid], b2[kHid], b3[kOut];
     __bf16 w1t[kHid][kK1];          // W1 transposed, rows padded with zeros
     __bf16 w2t[kHid][kHid];         // W2 transposed
@@ -59,8 +59,8 @@ struct InferArgs {
 
 hipError_t launch_infer(const InferArgs& a, hipStream_t s);
 
-// Training on standardised features F [m][kIn] and targets Y [m][2] (x_HI', standardised
-// log10 T'), minibatch rows given by idx.
+// Training on standardised features F [m][kIn] and standardised targets Y [m][2]
+// (x_HI' - x_HI, log10 (T'/T)), minibatch rows given by idx.
 struct TrainArgs {
     const Model* model;       // bf16 weights used by the forward pass
     const float* F;
@@ -84,11 +84,13 @@ struct AdamArgs {
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
 hipError_t launch_publish(const float* params, Model* model, hipStream_t s);
 
-// Forward pass only: predictions P [m][2] (x_HI', log10 T') for standardised features.
-hipError_t launch_predict(const Model* model, const float* F, uint32_t m, float* P, hipStream_t s);
+// Forward pass only: predictions P [m][2] = (x_HI', T') for raw samples X [m][5] =
+// (n_H, x_HI, T, Gamma_HI, dt); rows idx[i] of X if idx is given, else row i.
+hipError_t launch_predict(const Model* model, const float* X, const uint32_t* idx, uint32_t m, float* P,
+                          hipStream_t s);
 
-// Raw samples (n_H, x_HI, T, Gamma_HI, dt) and targets (x_HI', T') to features and
-// training targets; also min/max and sums for the standardisation.
+// Raw samples (n_H, x_HI, T, Gamma_HI, dt) and targets (x_HI', T') to unstandardised
+// features and training targets (x_HI' - x_HI, log10 (T'/T)).
 hipError_t launch_features(const float* X, const float* Y, uint32_t m, float* F, float* Yt, hipStream_t s);
 
 }  // namespace mlp

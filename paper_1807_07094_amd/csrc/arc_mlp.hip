@@ -2,7 +2,8 @@
 //
 // Network: 5 -> 64 -> 64 -> 2, tanh hidden units, BF16 weights and activations, FP32
 // accumulation (v_mfma_f32_16x16x32_bf16). Inputs: log10 n_H, x_HI, log10 T, log10 Gamma_HI,
-// log10 dt, standardised. Outputs: x_HI' through a sigmoid and standardised log10 T'.
+// log10 dt, standardised. Outputs: the standardised changes x_HI' - x_HI and log10 (T'/T),
+// added to the cell's own FP32 state.
 // Helium is not an input: the gate accepts a cell only when its helium is close to steady.
 //
 //   k_infer       per cell: features, MFMA forward, gate; accepted cells are written,
@@ -65,9 +66,13 @@ __device__ __forceinline__ float act(float x)  // tanh
     return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
 
-__device__ __forceinline__ float sigmoid(float x)
+
+// Orders one wave's LDS writes before its later reads by other lanes: LDS operations of
+// a wave complete in issue order; the fence keeps the compiler from moving accesses.
+__device__ __forceinline__ void wave_sync()
 {
-    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * fminf(fmaxf(x, -80.0f), 80.0f)));
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Forward pass of 64 rows held in LDS: X [64][kK1] -> H (in place, [64][kHid]) -> O [64][2].
@@ -93,13 +98,13 @@ __device__ __forceinline__ void forward64(const __bf16* X, __bf16* H, __bf16* H1
                 if (H1keep) H1keep[row * kHid + col] = h;
             }
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     // layer 2: [64 x 64] x [64 x 64], written back over the rows it reads
     for (int t = 0; t < 4; ++t) {
         f32x4 d[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) d[nt] = tile_mm(H, kHid, 1, w2t, 1, kHid, 16 * t, 16 * nt, kHid);
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
@@ -107,7 +112,7 @@ __device__ __forceinline__ void forward64(const __bf16* X, __bf16* H, __bf16* H1
                 const int row = 16 * t + 4 * q + r, col = 16 * nt + r16;
                 H[row * kHid + col] = (__bf16)act(d[nt][r] + b2[col]);
             }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
     }
     // layer 3: [64 x 64] x [64 x 16]
     for (int t = 0; t < 4; ++t) {
@@ -116,7 +121,7 @@ __device__ __forceinline__ void forward64(const __bf16* X, __bf16* H, __bf16* H1
 #pragma unroll
             for (int r = 0; r < 4; ++r) O[(16 * t + 4 * q + r) * kOut + r16] = d[r] + b3[r16];
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
 }
 
 // Model weights into LDS (called by the whole block).
@@ -163,12 +168,13 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(InferArgs a)
         const uint32_t c = base + lane;
         const bool valid = c < a.ncell;
         float f[kIn] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        float nh = 1.0f, T = 1.0f;
+        float nh = 1.0f, T = 1.0f, x0 = 0.0f;
         if (valid) {
             nh = a.n_h[c];
             T = a.temp[c];
+            x0 = a.x_hi[c];
             f[0] = log10f(nh);
-            f[1] = a.x_hi[c];
+            f[1] = x0;
             f[2] = log10f(T);
             f[3] = safe_log10(a.gamma[c], kGammaFloor);
             f[4] = ldt;
@@ -177,14 +183,14 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(InferArgs a)
 #pragma unroll
         for (int k = 0; k < kK1; ++k)
             X[lane * kK1 + k] = (__bf16)(k < kIn && valid ? (f[k] - M->in_mu[k]) / M->in_sd[k] : 0.0f);
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         forward64(X, hs[wid], nullptr, os[wid], sm.w1t, sm.w2t, sm.w3t, sm.b1, sm.b2, sm.b3);
         bool accept = false;
         float xn = 0.0f, Tn = 0.0f;
         if (valid) {
             const float o0 = os[wid][lane * kOut], o1 = os[wid][lane * kOut + 1];
-            xn = sigmoid(o0);
-            Tn = exp10f(o1 * M->t_sd + M->t_mu);
+            xn = fminf(fmaxf(x0 + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
+            Tn = T * exp10f(o1 * M->out_sd[1] + M->out_mu[1]);
             accept = true;
             if (a.gated) {
                 // (1) inside the training range, in a bin with enough samples and a small
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(InferArgs a)
                 }
                 accept = accept && M->gate_count[bin] >= a.gate_min_count && M->gate_err[bin] <= a.gate_tol;
                 // (2) physical outputs
-                accept = accept && xn >= 0.0f && xn <= 1.0f && Tn >= a.t_floor && Tn < 1e9f;
+                accept = accept && Tn >= a.t_floor && Tn < 1e9f;
                 // (3) helium close to steady over dt (the network does not see helium)
                 if (accept && a.y > 0.0) {
                     const double nhd = nh, nhe = a.y * nhd;
@@ -242,9 +248,19 @@ hipError_t launch_infer(const InferArgs& a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------------
-// Forward only (validation, gate calibration).
+// Forward only (validation, gate calibration, evaluation): raw samples to (x_HI', T').
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(64 * kInferWaves) void k_predict(const Model* M, const float* F, uint32_t m, float* P)
+__device__ __forceinline__ void raw_features(const float* x, float f[kIn])
+{
+    f[0] = log10f(x[0]);
+    f[1] = x[1];
+    f[2] = log10f(x[2]);
+    f[3] = safe_log10(x[3], kGammaFloor);
+    f[4] = log10f(x[4]);
+}
+
+__global__ __launch_bounds__(64 * kInferWaves) void k_predict(const Model* M, const float* X, const uint32_t* idx,
+                                                              uint32_t m, float* P)
 {
     __shared__ SharedModel sm;
     __shared__ __bf16 xs[kInferWaves][64 * kK1];
@@ -256,41 +272,42 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_predict(const Model* M, co
     for (uint32_t base = blockIdx.x * blockDim.x + 64 * wid; base < m; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + lane;
         const bool valid = i < m;
+        float f[kIn] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        const float* x = X + (size_t)(valid ? (idx ? idx[i] : i) : 0u) * 5;
+        if (valid) raw_features(x, f);
 #pragma unroll
-        for (int k = 0; k < kK1; ++k) xs[wid][lane * kK1 + k] = (__bf16)(k < kIn && valid ? F[(size_t)i * kIn + k] : 0.0f);
-        __builtin_amdgcn_wave_barrier();
+        for (int k = 0; k < kK1; ++k)
+            xs[wid][lane * kK1 + k] = (__bf16)(k < kIn && valid ? (f[k] - M->in_mu[k]) / M->in_sd[k] : 0.0f);
+        wave_sync();
         forward64(xs[wid], hs[wid], nullptr, os[wid], sm.w1t, sm.w2t, sm.w3t, sm.b1, sm.b2, sm.b3);
         if (valid) {
-            P[(size_t)i * 2] = sigmoid(os[wid][lane * kOut]);
-            P[(size_t)i * 2 + 1] = os[wid][lane * kOut + 1] * M->t_sd + M->t_mu;
+            const float o0 = os[wid][lane * kOut], o1 = os[wid][lane * kOut + 1];
+            P[(size_t)i * 2] = fminf(fmaxf(x[1] + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
+            P[(size_t)i * 2 + 1] = x[2] * exp10f(o1 * M->out_sd[1] + M->out_mu[1]);
         }
     }
 }
 
-hipError_t launch_predict(const Model* model, const float* F, uint32_t m, float* P, hipStream_t s)
+hipError_t launch_predict(const Model* model, const float* X, const uint32_t* idx, uint32_t m, float* P,
+                          hipStream_t s)
 {
     size_t blocks = (m + 64 * kInferWaves - 1) / (64 * kInferWaves);
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    k_predict<<<(unsigned)blocks, 64 * kInferWaves, 0, s>>>(model, F, m, P);
+    k_predict<<<(unsigned)blocks, 64 * kInferWaves, 0, s>>>(model, X, idx, m, P);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
-// Features and targets of raw samples (n_H, x_HI, T, Gamma_HI, dt) -> (x_HI', T').
+// Features and targets of raw samples (n_H, x_HI, T, Gamma_HI, dt) and (x_HI', T').
 // ---------------------------------------------------------------------------------
 __global__ void k_features(const float* X, const float* Y, uint32_t m, float* F, float* Yt)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
         const float* x = X + (size_t)i * 5;
-        float* f = F + (size_t)i * kIn;
-        f[0] = log10f(x[0]);
-        f[1] = x[1];
-        f[2] = log10f(x[2]);
-        f[3] = safe_log10(x[3], kGammaFloor);
-        f[4] = log10f(x[4]);
-        Yt[(size_t)i * 2] = Y[(size_t)i * 2];
-        Yt[(size_t)i * 2 + 1] = log10f(Y[(size_t)i * 2 + 1]);
+        raw_features(x, F + (size_t)i * kIn);
+        Yt[(size_t)i * 2] = Y[(size_t)i * 2] - x[1];
+        Yt[(size_t)i * 2 + 1] = log10f(Y[(size_t)i * 2 + 1]) - log10f(x[2]);
     }
 }
 
@@ -305,7 +322,8 @@ hipError_t launch_features(const float* X, const float* Y, uint32_t m, float* F,
 
 // ---------------------------------------------------------------------------------
 // Training: gradient of the minibatch loss
-//   L = sum_s (sigmoid(o0) - x')^2 + (o1 - t')^2     (divided by the batch size in Adam)
+//   L = sum_s (o0 - y0)^2 + (o1 - y1)^2     (standardised targets; divided by the batch
+//                                            size in Adam)
 // through the same BF16 forward as inference. One wave per block, 64 samples per wave.
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
@@ -335,17 +353,16 @@ __global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
             y1 = a.Y[(size_t)i * 2 + 1];
         }
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     forward64(X, H, H1, O, sm.w1t, sm.w2t, sm.w3t, sm.b1, sm.b2, sm.b3);
     // output gradient
     {
-        const float p = sigmoid(O[lane * kOut]);
-        const float g0 = valid ? 2.0f * (p - y0) * p * (1.0f - p) : 0.0f;
+        const float g0 = valid ? 2.0f * (O[lane * kOut] - y0) : 0.0f;
         const float g1 = valid ? 2.0f * (O[lane * kOut + 1] - y1) : 0.0f;
 #pragma unroll
         for (int k = 0; k < 32; ++k) DO[lane * 32 + k] = (__bf16)(k == 0 ? g0 : (k == 1 ? g1 : 0.0f));
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     float* P = a.partial + (size_t)blockIdx.x * kNParams;
     // dW3[k][n] = sum_s H2[s][k] dO[s][n]   (M = 64 k, N = 16 n, K = 64 s)
     for (int t = 0; t < 4; ++t) {
@@ -366,7 +383,7 @@ __global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
                 D2[row * kHid + col] = (__bf16)(d[r] * (1.0f - h * h));
             }
         }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     // dW2[k][n] = sum_s H1[s][k] dz2[s][n]     (M = 64, N = 64, K = 64)
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -387,7 +404,7 @@ __global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
                 D1[row * kHid + col] = (__bf16)(d[r] * (1.0f - h * h));
             }
         }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     // dW1[k][n] = sum_s X[s][k] dz1[s][n]      (M = 16 k (5 used), N = 64, K = 64)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {

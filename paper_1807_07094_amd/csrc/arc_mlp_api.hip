@@ -20,6 +20,7 @@ using namespace arc::mlp;
 namespace {
 
 constexpr uint32_t kMagic = 0x41524d31u;  // "ARM1"
+constexpr uint32_t kVersion = 2;           // residual outputs
 
 struct Blob {
     uint32_t magic, version, nparams, pad;
@@ -161,16 +162,16 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
         hm.lo[k] = lo;
         hm.hi[k] = hi > lo ? hi : lo + 1e-6f;
     }
-    {
+    for (int k = 0; k < kOut; ++k) {
         double s = 0, s2 = 0;
         for (uint32_t i : train) {
-            const double v = hY[(size_t)i * 2 + 1];
+            const double v = hY[(size_t)i * 2 + k];
             s += v;
             s2 += v * v;
         }
         const double mu = s / n_train, sd = std::sqrt(std::max(1e-12, s2 / n_train - mu * mu));
-        hm.t_mu = (float)mu;
-        hm.t_sd = (float)sd;
+        hm.out_mu[k] = (float)mu;
+        hm.out_sd[k] = (float)sd;
     }
     // gate counts from the training samples (raw features)
     for (uint32_t i : train) hm.gate_count[gate_bin(&hF[(size_t)i * kIn], hm.lo, hm.hi)]++;
@@ -178,7 +179,7 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
     std::vector<float> sF(hF), sY(hY);
     for (size_t i = 0; i < (size_t)m; ++i) {
         for (int k = 0; k < kIn; ++k) sF[i * kIn + k] = (hF[i * kIn + k] - hm.in_mu[k]) / hm.in_sd[k];
-        sY[i * 2 + 1] = (hY[i * 2 + 1] - hm.t_mu) / hm.t_sd;
+        for (int k = 0; k < kOut; ++k) sY[i * 2 + k] = (hY[i * 2 + k] - hm.out_mu[k]) / hm.out_sd[k];
     }
     TRY(hipMemcpyAsync(F, sF.data(), sF.size() * sizeof(float), hipMemcpyHostToDevice, st));
     TRY(hipMemcpyAsync(Yt, sY.data(), sY.size() * sizeof(float), hipMemcpyHostToDevice, st));
@@ -230,26 +231,26 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
         }
     }
 
-    // held-out predictions, errors and the gate calibration
-    std::vector<float> vF(n_val * kIn);
-    for (size_t j = 0; j < n_val; ++j)
-        for (int k = 0; k < kIn; ++k) vF[j * kIn + k] = sF[(size_t)val[j] * kIn + k];
-    float* dvF = nullptr;
-    TRY(hipMalloc((void**)&dvF, vF.size() * sizeof(float)));
-    guard.ptrs.push_back(dvF);
+    // held-out predictions (the inference arithmetic, from the raw samples), errors and
+    // the gate calibration: per bin the largest of |x_HI' error| and |T' error| / T'
+    std::vector<float> rY((size_t)m * 2);
+    TRY(hipMemcpyAsync(rY.data(), Y, rY.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    uint32_t* dval = nullptr;
+    TRY(hipMalloc((void**)&dval, n_val * sizeof(uint32_t)));
+    guard.ptrs.push_back(dval);
     TRY(hipMalloc((void**)&P, n_val * 2 * sizeof(float)));
     guard.ptrs.push_back(P);
-    TRY(hipMemcpyAsync(dvF, vF.data(), vF.size() * sizeof(float), hipMemcpyHostToDevice, st));
-    TRY(launch_predict(mlp->model, dvF, (uint32_t)n_val, P, st));
+    TRY(hipMemcpyAsync(dval, val.data(), n_val * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    TRY(launch_predict(mlp->model, X, dval, (uint32_t)n_val, P, st));
     std::vector<float> hP(n_val * 2);
     TRY(hipMemcpyAsync(hP.data(), P, hP.size() * sizeof(float), hipMemcpyDeviceToHost, st));
     TRY(hipStreamSynchronize(st));
     double se_x = 0, se_t = 0, emax = 0;
     for (size_t j = 0; j < n_val; ++j) {
         const uint32_t i = val[j];
-        const double ex = std::fabs((double)hP[2 * j] - hY[(size_t)i * 2]);
-        const double dl = (double)hP[2 * j + 1] - hY[(size_t)i * 2 + 1];
-        const double et = std::fabs(std::pow(10.0, dl) - 1.0);
+        const double ex = std::fabs((double)hP[2 * j] - (double)rY[(size_t)i * 2]);
+        const double et = std::fabs((double)hP[2 * j + 1] / (double)rY[(size_t)i * 2 + 1] - 1.0);
+        const double dl = std::log10((double)hP[2 * j + 1] / (double)rY[(size_t)i * 2 + 1]);
         se_x += ex * ex;
         se_t += dl * dl;
         const float e = (float)std::max(ex, et);
@@ -299,7 +300,7 @@ arc_status arc_mlp_save(const arc_mlp* mlp, void* buf, size_t* size)
     Blob* b = new (std::nothrow) Blob();
     if (!b) return ARC_E_NOMEM;
     b->magic = kMagic;
-    b->version = 1;
+    b->version = kVersion;
     b->nparams = kNParams;
     b->pad = 0;
     bool ok = hipMemcpy(&b->model, mlp->model, sizeof(Model), hipMemcpyDeviceToHost) == hipSuccess &&
@@ -316,7 +317,7 @@ arc_status arc_mlp_load(arc_mlp* mlp, const void* buf, size_t size)
     Blob* b = new (std::nothrow) Blob();
     if (!b) return ARC_E_NOMEM;
     std::memcpy(b, buf, sizeof(Blob));
-    if (b->magic != kMagic || b->version != 1 || b->nparams != (uint32_t)kNParams) {
+    if (b->magic != kMagic || b->version != kVersion || b->nparams != (uint32_t)kNParams) {
         delete b;
         return ARC_E_ARG;
     }
@@ -339,33 +340,9 @@ arc_status arc_mlp_predict(arc_ctx* ctx, const arc_mlp* mlp, const float* X, int
     if (m == 0) return ARC_OK;
     hipStream_t st = (hipStream_t)stream;
     if (hipSetDevice(mlp->device) != hipSuccess) return ARC_E_DEVICE;
-    float* F = nullptr;
-    float* Yd = nullptr;
-    std::vector<float> hF((size_t)m * kIn);
-    Model hm;
-    bool ok = hipMalloc((void**)&F, (size_t)m * kIn * sizeof(float)) == hipSuccess &&
-              hipMalloc((void**)&Yd, (size_t)m * 2 * sizeof(float)) == hipSuccess;
-    // the targets are unused here: pass the inputs' first two columns as dummies
-    ok = ok && launch_features(X, X, (uint32_t)m, F, Yd, st) == hipSuccess &&
-         hipMemcpyAsync(hF.data(), F, hF.size() * sizeof(float), hipMemcpyDeviceToHost, st) == hipSuccess &&
-         hipMemcpyAsync(&hm, mlp->model, sizeof hm, hipMemcpyDeviceToHost, st) == hipSuccess &&
-         hipStreamSynchronize(st) == hipSuccess;
-    if (ok) {
-        for (size_t i = 0; i < (size_t)m; ++i)
-            for (int k = 0; k < kIn; ++k) hF[i * kIn + k] = (hF[i * kIn + k] - hm.in_mu[k]) / hm.in_sd[k];
-        ok = hipMemcpyAsync(F, hF.data(), hF.size() * sizeof(float), hipMemcpyHostToDevice, st) == hipSuccess &&
-             launch_predict(mlp->model, F, (uint32_t)m, P, st) == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
-    }
-    // log10 T' -> T' on the host side of the copy would need another pass; do it on the device
-    if (ok) {
-        std::vector<float> hP((size_t)m * 2);
-        ok = hipMemcpy(hP.data(), P, hP.size() * sizeof(float), hipMemcpyDeviceToHost) == hipSuccess;
-        for (size_t i = 0; ok && i < (size_t)m; ++i) hP[2 * i + 1] = std::pow(10.0f, hP[2 * i + 1]);
-        ok = ok && hipMemcpy(P, hP.data(), hP.size() * sizeof(float), hipMemcpyHostToDevice) == hipSuccess;
-    }
-    if (F) (void)hipFree(F);
-    if (Yd) (void)hipFree(Yd);
-    return ok ? ARC_OK : arc::ctx_fail(ctx, ARC_E_DEVICE, "prediction failed");
+    if (m > (int64_t)UINT32_MAX) return arc::ctx_fail(ctx, ARC_E_ARG, "too many samples");
+    const hipError_t e = launch_predict(mlp->model, X, nullptr, (uint32_t)m, P, st);
+    return e == hipSuccess ? ARC_OK : arc::ctx_fail(ctx, ARC_E_DEVICE, "prediction failed: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

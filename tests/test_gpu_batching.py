@@ -1,0 +1,83 @@
+"""Batched schedule extras: graph replay and the autotuner.
+
+* replaying the recorded graphs gives the eager result bit for bit, on every replay,
+  with other GPU work and synchronisations between the replays, and a change of the
+  sources' luminosities (new fixed-point scales) is recorded afresh;
+* the autotuner's chosen shape, and the tuned schedule (tuned on first use), reach the
+  plain schedule's fixed-point field exactly.
+"""
+import numpy as np
+import pytest
+
+from helpers import run_gpu_trace
+from paper_1807_07094_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(arc):
+    c = arc.Context(0)
+    yield c
+    c.close()
+
+
+def test_graph_replays_equal_eager(arc, ctx):
+    import torch
+
+    w = W.lognormal(40, 12, 21)
+    eager = run_gpu_trace(arc, ctx, w, schedule="batched")
+    other = arc.Context(0)
+    try:
+        for rep in range(3):
+            got = run_gpu_trace(arc, ctx, w, schedule="batched", graph=True)
+            assert np.array_equal(got["J"], eager["J"]), rep
+            assert np.array_equal(got["gamma"], eager["gamma"]), rep
+            assert got["ledger"]["crossings"] == eager["ledger"]["crossings"]
+            assert got["ledger"]["absorbed"] == eager["ledger"]["absorbed"]
+            # unrelated eager work between replays
+            a = torch.randn(512, 512, device="cuda")
+            float((a @ a).sum())
+            run_gpu_trace(arc, other, W.lognormal(24, 3, 100 + rep), schedule="batched")
+            torch.cuda.synchronize()
+        # other luminosities: new fixed-point scales, recorded again
+        w2 = w.subset(np.arange(12))
+        w2.sources["ndot"] = w2.sources["ndot"] * np.linspace(0.5, 2.0, 12)
+        e2 = run_gpu_trace(arc, ctx, w2, schedule="batched")
+        g2 = run_gpu_trace(arc, ctx, w2, schedule="batched", graph=True)
+        assert np.array_equal(g2["J"], e2["J"])
+        assert not np.array_equal(e2["J"], eager["J"])
+    finally:
+        other.close()
+
+
+def test_autotuner_shape_matches_plain_bitwise(arc, ctx):
+    import torch
+
+    w = W.lognormal(40, 12, 22)
+    plain = run_gpu_trace(arc, ctx, w, schedule="plain")
+    g = arc.device_grid(w.grid)
+    gamma = torch.empty((3,) + w.shape, device="cuda")
+    heat = torch.empty_like(gamma)
+    res = ctx.autotune(g, w.sources, w.bins, w.dt, gamma, heat, level0=w.trace["level0"],
+                       rays_per_cell=w.trace["rays_per_cell"], eps_term=w.trace["eps_term"])
+    assert res["candidates"] >= 10
+    assert res["waves"] in (2, 4, 8) and res["waves_per_cu"] in (8, 12, 16)
+    assert res["refill"] in (4, 8, 16, 32) and -1 <= res["item_delta"] <= 2
+    assert 0 < res["ms_best"] <= res["ms_default"]
+    tuned = run_gpu_trace(arc, ctx, w, schedule="batched_tuned")
+    assert np.array_equal(tuned["J"], plain["J"])
+    tuned_graph = run_gpu_trace(arc, ctx, w, schedule="batched_tuned", graph=True)
+    assert np.array_equal(tuned_graph["J"], plain["J"])
+
+
+def test_tuned_schedule_tunes_on_first_use(arc):
+    w = W.lognormal(32, 9, 23)
+    fresh = arc.Context(0)
+    try:
+        plain = run_gpu_trace(arc, fresh, w, schedule="plain")
+        tuned = run_gpu_trace(arc, fresh, w, schedule="batched_tuned")
+        assert np.array_equal(tuned["J"], plain["J"])
+        assert tuned["ledger"]["crossings"] == plain["ledger"]["crossings"]
+    finally:
+        fresh.close()

@@ -30,7 +30,7 @@ def ctx(arc):
 def trained(arc, ctx):
     X, Y = learned.training_set(ctx, arc, n=120_000, seed=5, sizes=(48, 64), n_src=(32, 48))
     net = arc.MLP(ctx)
-    rep = net.train(X, Y, epochs=6, batch=1024, lr=2e-3, seed=3)
+    rep = net.train(X, Y, epochs=20, batch=1024, lr=2e-3, seed=3)
     return net, rep, X, Y
 
 
@@ -50,7 +50,7 @@ def parse_model(blob: bytes):
     off = 16  # magic, version, nparams, pad
     f = lambda n: (np.frombuffer(blob, np.float32, n, off), n * 4)
     out = {}
-    for name, n in (("in_mu", 5), ("in_sd", 5), ("lo", 5), ("hi", 5), ("t_mu", 1), ("t_sd", 1), ("b1", HID),
+    for name, n in (("in_mu", 5), ("in_sd", 5), ("lo", 5), ("hi", 5), ("out_mu", 2), ("out_sd", 2), ("b1", HID),
                     ("b2", HID), ("b3", 2)):
         a, nb = f(n)
         out[name] = a.copy()
@@ -64,14 +64,16 @@ def parse_model(blob: bytes):
 
 def reference_forward(m, X):
     """NumPy forward pass in the network's arithmetic: BF16 inputs, weights and hidden
-    activations, FP32 sums."""
+    activations, FP32 sums; outputs are changes added to the sample's own x_HI and log10 T.
+    Returns (x_HI', log10 T')."""
     f = np.stack([np.log10(X[:, 0]), X[:, 1], np.log10(X[:, 2]), np.log10(np.maximum(X[:, 3], 1e-30)),
                   np.log10(X[:, 4])], axis=1).astype(np.float32)
     x = f32_to_bf16((f - m["in_mu"]) / m["in_sd"])
     h1 = f32_to_bf16(np.tanh(x @ m["w1t"][:, :5].T + m["b1"]))
     h2 = f32_to_bf16(np.tanh(h1 @ m["w2t"].T + m["b2"]))
     o = h2 @ m["w3t"][:2].T + m["b3"]
-    return 1.0 / (1.0 + np.exp(-o[:, 0])), o[:, 1] * m["t_sd"][0] + m["t_mu"][0]
+    x_new = np.clip(X[:, 1] + (o[:, 0] * m["out_sd"][0] + m["out_mu"][0]), 0.0, 1.0)
+    return x_new, np.log10(X[:, 2]) + (o[:, 1] * m["out_sd"][1] + m["out_mu"][1])
 
 
 def test_training_report(trained):
