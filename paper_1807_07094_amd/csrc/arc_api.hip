@@ -33,6 +33,7 @@ struct arc_ctx {
     SourceRec* src = nullptr;
     double* src_pos = nullptr;
     double* src_ndot = nullptr;
+    uint32_t* src_order = nullptr;
     int src_cap = 0;
     // HEALPix centres, levels 0..dirs_levels-1
     float4* dirs = nullptr;
@@ -250,7 +251,7 @@ void arc_destroy(arc_ctx* c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    void* bufs[] = {c->kappa, c->J, c->src, c->src_pos, c->src_ndot, c->dirs, c->rays[0], c->rays[1],
+    void* bufs[] = {c->kappa, c->J, c->src, c->src_pos, c->src_ndot, c->src_order, c->dirs, c->rays[0], c->rays[1],
                     c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats, c->fallback};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
@@ -292,6 +293,7 @@ struct TracePlan {
     RayRec* rays1;
     RayRec* spill;
     uint32_t* u32;
+    const uint32_t* order;  // sources by decreasing photon rate (work-queue order)
 };
 
 // Validation, fixed-point units, buffers and launch arguments shared by both schedules.
@@ -365,12 +367,15 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
             if (c->src) HIP_TRY(c, hipFree(c->src));
             if (c->src_pos) HIP_TRY(c, hipFree(c->src_pos));
             if (c->src_ndot) HIP_TRY(c, hipFree(c->src_ndot));
+            if (c->src_order) HIP_TRY(c, hipFree(c->src_order));
             c->src = nullptr;
             c->src_pos = c->src_ndot = nullptr;
+            c->src_order = nullptr;
             c->src_cap = 0;
             HIP_TRY(c, hipMalloc((void**)&c->src, s->n * sizeof(SourceRec)));
             HIP_TRY(c, hipMalloc((void**)&c->src_pos, s->n * 3 * sizeof(double)));
             HIP_TRY(c, hipMalloc((void**)&c->src_ndot, s->n * sizeof(double)));
+            HIP_TRY(c, hipMalloc((void**)&c->src_order, s->n * sizeof(uint32_t)));
             c->src_cap = s->n;
         }
     }
@@ -497,6 +502,7 @@ arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int re
     P.rays1 = c->rays[1];
     P.spill = c->spill;
     P.u32 = c->u32;
+    P.order = c->src_order;
     return ARC_OK;
 }
 
@@ -520,7 +526,7 @@ hipError_t enqueue_levels(const TracePlan& P, hipStream_t st)
 {
     hipError_t e;
     if (P.nsrc == 0) return hipSuccess;
-    if ((e = launch_seed_roots(0, (uint32_t)P.nsrc, P.A.level0, P.rays0, st)) != hipSuccess) return e;
+    if ((e = launch_seed_roots(0, (uint32_t)P.nsrc, P.A.level0, P.order, P.rays0, st)) != hipSuccess) return e;
     uint32_t* cnt = P.u32 + 2;  // [2], [3]: ray counts of consecutive levels
     if ((e = launch_set_u32(cnt, (uint32_t)P.n_roots, st)) != hipSuccess) return e;
     size_t bound = (size_t)P.n_roots;
@@ -565,7 +571,7 @@ arc_status run_plain(arc_ctx* c, const TracePlan& P, hipStream_t st)
             HIP_TRY(c, grow(&c->rays[1], &cap2, 4 * n * sizeof(RayRec)));
             c->rays_cap = 4 * n;
         }
-        HIP_TRY(c, launch_seed_roots((uint32_t)si, 1, P.A.level0, c->rays[0], st));
+        HIP_TRY(c, launch_seed_roots((uint32_t)si, 1, P.A.level0, nullptr, c->rays[0], st));
         int cur = 0;
         while (n > 0) {
             const size_t need = 4 * n;
@@ -642,11 +648,21 @@ arc_status ensure_graphs(arc_ctx* c, const TracePlan& P)
 arc_status run_trace(arc_ctx* c, const TracePlan& P, const arc_sources* s, double dt, int schedule, bool graph,
                      hipStream_t st, arc_ledger* ledger)
 {
+    const bool batched = schedule != ARC_SCHED_PLAIN;
+    std::vector<uint32_t> order;
     if (s->n > 0) {
         HIP_TRY(c, hipMemcpyAsync(c->src_pos, s->pos, s->n * 3 * sizeof(double), hipMemcpyHostToDevice, st));
         HIP_TRY(c, hipMemcpyAsync(c->src_ndot, s->ndot, s->n * sizeof(double), hipMemcpyHostToDevice, st));
+        if (batched) {
+            // the work queue starts with the brightest sources, whose rays travel furthest, so
+            // that the longest subtrees are not the last ones taken (the field does not depend
+            // on the order: integer sums)
+            order.resize(s->n);
+            for (int i = 0; i < s->n; ++i) order[i] = (uint32_t)i;
+            std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b2) { return s->ndot[a] > s->ndot[b2]; });
+            HIP_TRY(c, hipMemcpyAsync(c->src_order, order.data(), s->n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        }
     }
-    const bool batched = schedule != ARC_SCHED_PLAIN;
     c->timed_kernel = false;
     if (batched && graph) {
         arc_status rc = ensure_graphs(c, P);

@@ -516,7 +516,7 @@ __device__ __forceinline__ StackRec<NB> child_stack(const Ray<NB>& ray, int k)
 // lane's cell are issued by NB adjacent lanes of the same instruction: instruction k,
 // lane j adds bin (64k + j) mod NB of crossing (64k + j) / NB.
 #ifndef ARC_DEDUP
-#define ARC_DEDUP 1
+#define ARC_DEDUP 1  // 0: every lane's crossing deposited on its own
 #endif
 constexpr int kDepSlots = 128;  // hash slots per wave, power of two
 
@@ -611,120 +611,14 @@ __device__ __forceinline__ void deposit_wave(const TraceArgs& A, const Dep<NB>& 
         deposit_wave_plain<NB>(A, d);
 }
 
-// Wave-wide deposit of one pass. Mode 1 sums the lanes' crossings of the same cell
-// within each call (deposit_wave_dedup); mode 2 keeps a per-wave LDS table of cell sums
-// over the K calls of a pass and emits it at the flush, so that crossings of one cell by
-// different lanes in different segments of the pass also cost one set of atomics.
-template <int NB>
-struct DepTable {
-    uint32_t slot_cell[kDepSlots];           // kNoCell = empty
-    unsigned long long acc[kDepSlots][NB];   // zero when empty
-    uint32_t cell[64];                       // staging of the lanes that lost their slot
-    unsigned long long q[64][NB];
-};
-
-template <int NB>
-__device__ __forceinline__ void dep_table_clear(DepTable<NB>* T)
-{
-    const int lane = threadIdx.x & 63;
-    volatile uint32_t* sc = T->slot_cell;
-    for (int i = lane; i < kDepSlots; i += 64) {
-        sc[i] = kNoCell;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) *(volatile unsigned long long*)&T->acc[i][b] = 0ull;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-}
-
-// Transposed emission of n staged items: instruction k, lane j adds bin (64k + j) mod NB
-// of item (64k + j) / NB; item i's cell and sums come from cell_of(i), q_of(i, bin).
-template <int NB, class CellOf, class QOf>
-__device__ __forceinline__ void emit_items(const TraceArgs& A, int n, CellOf cell_of, QOf q_of)
-{
-    const int lane = threadIdx.x & 63;
-    const int tot = n * NB;
-    for (int s = lane; s < tot; s += 64) {
-        const int item = s / NB, bin = s - item * NB;
-        const unsigned long long q = q_of(item, bin);
-        if (q != 0) atomicAdd(A.J + (size_t)cell_of(item) * (size_t)A.nbp + (size_t)bin, q);
-    }
-}
-
+// Wave-wide deposit of the crossings of one pass: add() once per segment, by every lane.
 template <int NB>
 struct Depositor {
     const TraceArgs& A;
-    void* scratch;
-#if ARC_DEDUP == 2
-    __device__ void add(const Dep<NB>& d)
-    {
-        DepTable<NB>* T = (DepTable<NB>*)scratch;
-        volatile uint32_t* sc = T->slot_cell;
-        const bool v = d.cell != kNoCell;
-        const uint32_t h = (d.cell * 2654435761u) >> (32 - 7);
-        bool in = false;
-        if (v) {
-            const uint32_t c0 = sc[h];
-            in = c0 == d.cell;
-            if (c0 == kNoCell) sc[h] = d.cell;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        if (v && !in) in = sc[h] == d.cell;
-        if (in) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                if (d.q[b] != 0) atomicAdd(&T->acc[h][b], (unsigned long long)d.q[b]);
-        }
-        const bool lose = v && !in;
-        const uint64_t lm = __ballot(lose);
-        if (lm) {
-            const int rank = __popcll(lm & __lanemask_lt());
-            if (lose) {
-                ((volatile uint32_t*)T->cell)[rank] = d.cell;
-#pragma unroll
-                for (int b = 0; b < NB; ++b) *(volatile unsigned long long*)&T->q[rank][b] = (unsigned long long)d.q[b];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            emit_items<NB>(
-                A, __popcll(lm), [&](int i) { return ((volatile uint32_t*)T->cell)[i]; },
-                [&](int i, int b) { return *(volatile unsigned long long*)&T->q[i][b]; });
-        }
-    }
-    __device__ void init() { dep_table_clear<NB>((DepTable<NB>*)scratch); }
-    __device__ void flush()
-    {
-        DepTable<NB>* T = (DepTable<NB>*)scratch;
-        volatile uint32_t* sc = T->slot_cell;
-        volatile uint32_t* list = T->cell;
-        const int lane = threadIdx.x & 63;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        // per 64 slots: the occupied ones, compacted, then emitted
-        for (int i0 = 0; i0 < kDepSlots; i0 += 64) {
-            const bool occ = sc[i0 + lane] != kNoCell;
-            const uint64_t om = __ballot(occ);
-            if (om == 0) continue;
-            if (occ) list[__popcll(om & __lanemask_lt())] = (uint32_t)(i0 + lane);
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            emit_items<NB>(
-                A, __popcll(om), [&](int i) { return sc[list[i]]; },
-                [&](int i, int b) { return *(volatile unsigned long long*)&T->acc[list[i]][b]; });
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        }
-        dep_table_clear<NB>(T);
-    }
-#else
-    __device__ void init() {}
-    __device__ void add(const Dep<NB>& d) { deposit_wave<NB>(A, d, (DepScratch<NB>*)scratch); }
+    DepScratch<NB>* scratch;
+    __device__ void add(const Dep<NB>& d) { deposit_wave<NB>(A, d, scratch); }
     __device__ void flush() {}
-#endif
 };
-
-#if ARC_DEDUP == 2
-template <int NB>
-using DepLds = DepTable<NB>;
-#else
-template <int NB>
-using DepLds = DepScratch<NB>;
-#endif
 
 // Wave-level reduction and flush of lane statistics into the global counters.
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)

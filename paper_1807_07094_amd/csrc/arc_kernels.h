@@ -59,7 +59,10 @@ hipError_t launch_opacity(const OpacityArgs& a, hipStream_t s);
 hipError_t launch_healpix(int level, float4* out, hipStream_t s);
 hipError_t launch_sources(int n, const double* pos, const double* ndot, const double* frac_over_12uj, int nb,
                           SourceRec* out, hipStream_t s);
-hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, RayRec* out, hipStream_t s);
+// Root rays of sources first_src .. first_src + nsrc - 1, or of order[0 .. nsrc) if order
+// is given (source k's rays are contiguous, in pixel order).
+hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, const uint32_t* order, RayRec* out,
+                             hipStream_t s);
 // n_in_dev (optional) holds the ray count on the device; n_in bounds it and sizes the grid.
 hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, const uint32_t* n_in_dev, uint32_t n_in,
                              RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s);

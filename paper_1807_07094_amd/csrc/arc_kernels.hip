@@ -3,7 +3,7 @@
 //   k_opacity          optical depth per cell length for every bin, field zeroing, input checks
 //   k_healpix          FP32 HEALPix pixel centres of one level (computed in FP64)
 //   k_sources          per-source table (lattice position, root-ray photon rate)
-//   k_seed_roots       root rays of a range of sources
+//   k_seed_roots       root rays of a range of sources (or of sources in a given order)
 //   k_trace_rays       one ray per lane, rays of one HEALPix level (the per-level schedule)
 //   k_trace_persistent every source in one launch: device work queue, wave-ballot refill,
 //                      per-wave LDS ray stack with a private spill area in memory
@@ -261,13 +261,14 @@ hipError_t launch_sources(int n, const double* pos, const double* ndot, const do
     return hipGetLastError();
 }
 
-__global__ void k_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, RayRec* out)
+__global__ void k_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, const uint32_t* order, RayRec* out)
 {
     const uint32_t npix = 12u << (2 * level0);
     const size_t n = (size_t)nsrc * npix;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         RayRec r;
-        r.src = first_src + (uint32_t)(i / npix);
+        const uint32_t k = (uint32_t)(i / npix);
+        r.src = order ? order[k] : first_src + k;
         r.lp = ((uint32_t)level0 << kLevelShift) | (uint32_t)(i % npix);
         r.pad0 = r.pad1 = 0;
 #pragma unroll
@@ -276,10 +277,11 @@ __global__ void k_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, RayR
     }
 }
 
-hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, RayRec* out, hipStream_t s)
+hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, const uint32_t* order, RayRec* out,
+                             hipStream_t s)
 {
     const size_t n = (size_t)nsrc * (12u << (2 * level0));
-    k_seed_roots<<<grid_for(n, 256), 256, 0, s>>>(first_src, nsrc, level0, out);
+    k_seed_roots<<<grid_for(n, 256), 256, 0, s>>>(first_src, nsrc, level0, order, out);
     return hipGetLastError();
 }
 
@@ -294,9 +296,8 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
                                                     RayRec* __restrict__ out, uint32_t* n_out, uint32_t out_cap)
 {
     const uint32_t n_in = n_in_dev ? *n_in_dev : n_in_host;
-    __shared__ DepLds<NB> dscr[4];
+    __shared__ DepScratch<NB> dscr[4];
     Depositor<NB> dep{A, dscr + (threadIdx.x >> 6)};
-    dep.init();
     LaneStats st;
     st.clear();
     const int lane = threadIdx.x & 63;
@@ -386,14 +387,13 @@ __global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, cons
 {
     using SRec = StackRec<NB>;
     __shared__ SRec lds[WPB * kStackCap];
-    __shared__ DepLds<NB> dscr[WPB];
+    __shared__ DepScratch<NB> dscr[WPB];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint64_t lt = __lanemask_lt();
     const uint32_t n_items = *n_items_dev;
     SRec* stk = lds + wid * kStackCap;
     Depositor<NB> dep{A, dscr + wid};
-    dep.init();
     // the spill area is sized in full records; compact records fit in it
     SRec* spill = reinterpret_cast<SRec*>(spill_all + (size_t)(blockIdx.x * WPB + wid) * spill_cap);
     int base = 0;          // ring start (oldest entry), wave-uniform

@@ -50,14 +50,20 @@ def sample_states(ctx, arc_mod, w: W.Workload, n: int, seed: int, steps: int = 3
             sel = np.flatnonzero(which == j)
             if sel.size == 0:
                 continue
-            sel_t = torch.from_numpy(sel).cuda()
-            sub = {"n_h": flat["n_h"][sel_t].contiguous().reshape(1, 1, -1), "cell_cm": w.grid["cell_cm"],
+            # the selected cells as a grid of rows of at most 1024 (padded with copies of
+            # the last cell; the padding is dropped afterwards)
+            rows = -(-sel.size // 1024)
+            width = min(1024, sel.size)
+            pad = np.concatenate([sel, np.full(rows * width - sel.size, sel[-1])])
+            sel_t = torch.from_numpy(pad).cuda()
+            sub = {"n_h": flat["n_h"][sel_t].contiguous().reshape(1, rows, width), "cell_cm": w.grid["cell_cm"],
                    "y_he": w.grid["y_he"]}
             for k in ("x_hi", "x_hei", "x_heii", "temp"):
-                sub[k] = flat[k][sel_t].contiguous().reshape(1, 1, -1)
+                sub[k] = flat[k][sel_t].contiguous().reshape(1, rows, width)
             ctx.chem_step(sub, gam[:, sel_t].contiguous(), hea[:, sel_t].contiguous(), float(dts[j]), **w.chem)
+            keep = torch.from_numpy(sel).cuda()
             for k in ("x_hi", "x_hei", "x_heii", "temp"):
-                out[k][sel_t] = sub[k].reshape(-1)
+                out[k][keep] = sub[k].reshape(-1)[: sel.size]
         dt_col = torch.from_numpy(dts[which].astype(np.float32)).cuda()
         xs.append(torch.stack([flat["n_h"], flat["x_hi"], flat["temp"], gam[0], dt_col], dim=1))
         ys.append(torch.stack([out["x_hi"], out["temp"]], dim=1))

@@ -34,7 +34,8 @@ def test_graph_replays_equal_eager(arc, ctx):
             assert np.array_equal(got["J"], eager["J"]), rep
             assert np.array_equal(got["gamma"], eager["gamma"]), rep
             assert got["ledger"]["crossings"] == eager["ledger"]["crossings"]
-            assert got["ledger"]["absorbed"] == eager["ledger"]["absorbed"]
+            # FP64 atomics of the ledger sum in a run-dependent order
+            assert abs(got["ledger"]["absorbed"] / eager["ledger"]["absorbed"] - 1) <= 1e-12
             # unrelated eager work between replays
             a = torch.randn(512, 512, device="cuda")
             float((a @ a).sum())
