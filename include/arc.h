@@ -190,13 +190,17 @@ arc_status arc_healpix_dirs(arc_ctx* ctx, int32_t level, float* dst, void* strea
 #define ARC_CHEM_MLP_GATED 1  /* learned step where its gate accepts the cell, plain elsewhere */
 #define ARC_CHEM_MLP_ONLY 2   /* learned step in every cell (evaluation of the network only) */
 
-/* Learned chemistry: a 5 -> 64 -> 64 -> 2 network (BF16 weights and activations, FP32
- * accumulation on the matrix cores) that maps (n_H, x_HI, T, Gamma_HI, dt) to (x_HI', T')
- * in place of the sub-cycled update of section 2.7. It does not see helium or the heating
- * rates; its gate accepts a cell only when (1) the inputs fall inside the training range
- * in a 8^5 occupancy bin with at least gate_min_count training samples whose held-out
- * error (max of |x_HI' error| and relative T' error) is <= gate_tol, (2) the outputs are
- * physical, and (3) helium is close to steady over dt. Other cells run the plain solver. */
+/* Learned chemistry: an 8 -> 64 -> 64 -> 2 network (ReLU; BF16 weights and activations, FP32
+ * accumulation on the matrix cores) in place of the sub-cycled update of section 2.7. Inputs
+ * (n_H, x_HI, T, Gamma_HI, dt, h, x_HeII, x_HeI), with h = H_HI x_HI + y (H_HeI x_HeI + H_HeII
+ * x_HeII) the photoheating per hydrogen atom. Outputs: log10(T'/T) and the correction of
+ * x_HI' to an exact exponential relaxation of x_HI with the recombination, collisional and
+ * photoionisation rates of the start of the step. It does not predict helium; its gate
+ * accepts a cell only when (1) the first five inputs fall inside the training range in a 8^5
+ * occupancy bin with at least gate_min_count training samples, whose held-out error, taken
+ * twice over, is <= gate_tol (the error of a sample is the larger of |x_HI' error| and
+ * |T' error| / (10 T')), (2) the output temperature is physical, and (3) helium is close to
+ * steady over dt. Other cells run the plain solver. */
 typedef struct arc_mlp arc_mlp;
 
 typedef struct {
@@ -206,6 +210,8 @@ typedef struct {
     uint32_t seed;         /* initialisation and shuffling */
     double val_frac;       /* share of the samples held out for the gate (0 < v < 1) */
     void* stream;          /* hipStream_t, NULL = default stream */
+    double y_he;           /* n_He / n_H of the samples' gas (for the x_HI baseline) */
+    int32_t collisional;   /* the samples' solver included collisional ionisation */
 } arc_train_params;
 
 typedef struct {
@@ -220,17 +226,17 @@ typedef struct {
 /* Create an untrained network owned by the caller (release with arc_mlp_destroy). */
 arc_status arc_mlp_create(arc_ctx* ctx, arc_mlp** out);
 void arc_mlp_destroy(arc_mlp* mlp);
-/* Train on m device samples: X [m][5] = (n_H [cm^-3], x_HI, T [K], Gamma_HI [1/s], dt [s]),
- * Y [m][2] = (x_HI', T' [K]) from the plain solver. All inputs must be finite with
- * n_H, T, dt > 0. Fits the standardisation, trains, then calibrates the gate on the
- * held-out samples. */
+/* Train on m device samples: X [m][8] = (n_H [cm^-3], x_HI, T [K], Gamma_HI [1/s], dt [s],
+ * h [erg/s], x_HeII, x_HeI), Y [m][2] = (x_HI', T' [K]) from the plain solver. All inputs must be
+ * finite with n_H, T, dt > 0. Fits the standardisation, trains, then calibrates the gate on
+ * the held-out samples. */
 arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float* Y, int64_t m,
                          const arc_train_params* params, arc_train_report* report);
 /* Network (weights, standardisation, gate) as a byte blob: with buf == NULL, *size
  * receives the size; otherwise buf must hold *size bytes. */
 arc_status arc_mlp_save(const arc_mlp* mlp, void* buf, size_t* size);
 arc_status arc_mlp_load(arc_mlp* mlp, const void* buf, size_t size);
-/* Predictions for device samples X [m][5] (same units as training) into device P [m][2]
+/* Predictions for device samples X [m][8] (same units as training) into device P [m][2]
  * = (x_HI', T' [K]), without the gate. */
 arc_status arc_mlp_predict(arc_ctx* ctx, const arc_mlp* mlp, const float* X, int64_t m, float* P, void* stream);
 

@@ -84,7 +84,7 @@ class ChemStats(C.Structure):
 
 class TrainParams(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("seed", C.c_uint32),
-                ("val_frac", C.c_double), ("stream", C.c_void_p)]
+                ("val_frac", C.c_double), ("stream", C.c_void_p), ("y_he", C.c_double), ("collisional", C.c_int32)]
 
 
 class TrainReport(C.Structure):
@@ -289,15 +289,25 @@ class MLP:
         except Exception:
             pass
 
-    def train(self, X, Y, epochs=8, batch=1024, lr=2e-3, seed=1, val_frac=0.1, stream=None) -> dict:
-        """X: device float32 [m, 5] (n_H, x_HI, T, Gamma_HI, dt); Y: device float32 [m, 2] (x_HI', T')."""
-        p = TrainParams(int(epochs), int(batch), float(lr), int(seed), float(val_frac), _stream(stream))
+    N_IN = 8  # (n_H, x_HI, T, Gamma_HI, dt, h, x_HeII, x_HeI)
+
+    def train(self, X, Y, epochs=8, batch=1024, lr=2e-3, seed=1, val_frac=0.1, stream=None, y_he=0.08,
+              collisional=1) -> dict:
+        """X: device float32 [m, 8] (n_H, x_HI, T, Gamma_HI, dt, h, x_HeII, x_HeI) with h the
+        photoheating per H atom; Y: device float32 [m, 2] (x_HI', T'). y_he and collisional
+        describe the samples' gas and solver."""
+        if tuple(X.shape[1:]) != (self.N_IN,) or tuple(Y.shape) != (X.shape[0], 2):
+            raise ValueError(f"expected X [m, {self.N_IN}] and Y [m, 2], got {tuple(X.shape)}, {tuple(Y.shape)}")
+        p = TrainParams(int(epochs), int(batch), float(lr), int(seed), float(val_frac), _stream(stream),
+                        float(y_he), int(collisional))
         rep = TrainReport()
         self._ctx._check(lib().arc_mlp_train(self._ctx._h, self._h, _ptr(X), _ptr(Y), int(X.shape[0]), C.byref(p),
                                              C.byref(rep)))
         return {k: getattr(rep, k) for k, _ in TrainReport._fields_}
 
     def predict(self, X, P, stream=None):
+        if tuple(X.shape[1:]) != (self.N_IN,) or tuple(P.shape) != (X.shape[0], 2):
+            raise ValueError(f"expected X [m, {self.N_IN}] and P [m, 2], got {tuple(X.shape)}, {tuple(P.shape)}")
         self._ctx._check(lib().arc_mlp_predict(self._ctx._h, self._h, _ptr(X), int(X.shape[0]), _ptr(P),
                                                _stream(stream)))
         return P

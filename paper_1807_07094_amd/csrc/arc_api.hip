@@ -51,6 +51,7 @@ struct arc_ctx {
     int* errflag = nullptr;
     unsigned long long* chem_stats = nullptr;
     uint32_t* fallback = nullptr;             // learned step: cells for the plain solver
+    uint32_t* seg_counts = nullptr;           // learned step: per list segment, stride 16
     size_t fallback_cap = 0;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool timed_kernel = false;  // ev[4], ev[5] bracket the dominant trace kernel
@@ -252,7 +253,7 @@ void arc_destroy(arc_ctx* c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     void* bufs[] = {c->kappa, c->J, c->src, c->src_pos, c->src_ndot, c->src_order, c->dirs, c->rays[0], c->rays[1],
-                    c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats, c->fallback};
+                    c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats, c->fallback, c->seg_counts};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < 6; ++i)
@@ -1000,19 +1001,24 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     a.t_floor = p->t_floor;
     a.stats = c->chem_stats;
     a.list = nullptr;
-    a.n_list = nullptr;
+    a.counts = nullptr;
+    a.seg = a.nseg = 0;
     HIP_TRY(c, launch_zero_u64(c->chem_stats, 4, st));
     HIP_TRY(c, hipEventRecord(c->ev[0], st));
-    uint32_t n_fb = 0;
+    uint64_t n_fb = 0;
+    std::vector<uint32_t> seg_counts;
     if (p->mode != ARC_CHEM_PLAIN) {
-        if (a.ncell > c->fallback_cap) {
+        const uint32_t seg = list_seg_cap(a.ncell);
+        const size_t need = (size_t)seg * kListSegs;
+        if (need > c->fallback_cap) {
             if (c->fallback) HIP_TRY(c, hipFree(c->fallback));
             c->fallback = nullptr;
             c->fallback_cap = 0;
-            HIP_TRY(c, hipMalloc((void**)&c->fallback, (size_t)a.ncell * sizeof(uint32_t)));
-            c->fallback_cap = a.ncell;
+            HIP_TRY(c, hipMalloc((void**)&c->fallback, need * sizeof(uint32_t)));
+            c->fallback_cap = need;
         }
-        HIP_TRY(c, launch_set_u32(c->u32 + 3, 0u, st));
+        if (!c->seg_counts) HIP_TRY(c, hipMalloc((void**)&c->seg_counts, 16 * kListSegs * sizeof(uint32_t)));
+        HIP_TRY(c, launch_zero_u64((unsigned long long*)c->seg_counts, 8 * kListSegs, st));
         mlp::InferArgs ia{};
         ia.model = p->mlp->model;
         ia.ncell = a.ncell;
@@ -1030,16 +1036,21 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
         ia.gate_min_count = (uint32_t)std::max(0, p->gate_min_count);
         ia.t_floor = (float)p->t_floor;
         ia.fallback = c->fallback;
-        ia.n_fallback = c->u32 + 3;
+        ia.seg_counts = c->seg_counts;
+        ia.seg = seg;
         ia.collisional = p->rates == 1 ? p->collisional : 0;
         HIP_TRY(c, mlp::launch_infer(ia, st));
         HIP_TRY(c, hipEventRecord(c->ev[2], st));
         if (p->mode == ARC_CHEM_MLP_GATED) {
             a.list = c->fallback;
-            a.n_list = c->u32 + 3;
+            a.counts = c->seg_counts;
+            a.seg = seg;
+            a.nseg = kListSegs;
             HIP_TRY(c, launch_chem(a, st));
         }
-        HIP_TRY(c, hipMemcpyAsync(&n_fb, c->u32 + 3, sizeof n_fb, hipMemcpyDeviceToHost, st));
+        seg_counts.resize(16 * kListSegs);
+        HIP_TRY(c, hipMemcpyAsync(seg_counts.data(), c->seg_counts, seg_counts.size() * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, st));
     } else {
         HIP_TRY(c, launch_chem(a, st));
     }
@@ -1047,6 +1058,7 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     unsigned long long cs[4];
     HIP_TRY(c, hipMemcpyAsync(cs, c->chem_stats, sizeof cs, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
+    for (uint32_t j = 0; j < seg_counts.size() / 16; ++j) n_fb += seg_counts[16 * j];
     if (stats) {
         stats->cells = a.ncell;
         stats->sub_total = (int64_t)cs[0];

@@ -439,7 +439,7 @@ __device__ __forceinline__ int deposit_seg(const TraceArgs& A, Ray<NB>& ray, con
 // Segments whose geometry is computed ahead of their deposits (opacity loads in flight
 // per lane).
 #ifndef ARC_SEG_AHEAD
-#define ARC_SEG_AHEAD 3
+#define ARC_SEG_AHEAD 4
 #endif
 constexpr int kSegAhead = ARC_SEG_AHEAD;
 

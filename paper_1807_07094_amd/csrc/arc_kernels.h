@@ -46,9 +46,17 @@ struct ChemArgs {
     int isothermal, rates, collisional, max_sub;
     double alpha_hii, eps, t_floor;
     unsigned long long* stats;  // [0] sub total, [1] capped, [2] max
-    const uint32_t* list;       // optional: update only cells list[0 .. *n_list)
-    const uint32_t* n_list;
+    // optional cell list in segments: segment j holds list[j * seg .. j * seg + counts[16 j])
+    const uint32_t* list;
+    const uint32_t* counts;
+    uint32_t seg, nseg;
 };
+
+// Fallback lists of the learned step: tile t (64 cells) appends to segment t mod kListSegs,
+// whose counter sits alone in a 64-byte line (counts[16 j]); a segment holds at most
+// ceil(tiles / kListSegs) * 64 cells.
+constexpr uint32_t kListSegs = 1024;
+inline uint32_t list_seg_cap(uint32_t ncell) { return ((ncell + 63) / 64 + kListSegs - 1) / kListSegs * 64; }
 
 hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);

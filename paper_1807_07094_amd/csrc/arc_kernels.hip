@@ -619,9 +619,14 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a)
 {
     unsigned long long sub_total = 0, capped = 0;
     unsigned int sub_max = 0;
-    const uint32_t n_todo = a.list ? *a.n_list : a.ncell;
-    for (uint32_t ii = blockIdx.x * blockDim.x + threadIdx.x; ii < n_todo; ii += gridDim.x * blockDim.x) {
-        const uint32_t c = a.list ? a.list[ii] : ii;
+    const size_t n_todo = a.list ? (size_t)a.seg * a.nseg : a.ncell;
+    for (size_t ii = blockIdx.x * (size_t)blockDim.x + threadIdx.x; ii < n_todo; ii += (size_t)gridDim.x * blockDim.x) {
+        uint32_t c = (uint32_t)ii;
+        if (a.list) {
+            const uint32_t j = (uint32_t)(ii / a.seg), off = (uint32_t)(ii - (size_t)j * a.seg);
+            if (off >= a.counts[16 * j]) continue;
+            c = a.list[ii];
+        }
         const double nh = a.n_h[c], nhe = a.y * nh;
         double nhi = nh * (double)a.x_hi[c], nhii = nh - nhi;
         double nhei = nhe * (double)a.x_hei[c], nheii = nhe * (double)a.x_heii[c];
@@ -712,7 +717,7 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a)
 
 hipError_t launch_chem(const ChemArgs& a, hipStream_t s)
 {
-    k_chem<<<grid_for(a.ncell, 256, 1u << 16), 256, 0, s>>>(a);
+    k_chem<<<grid_for(a.list ? (size_t)a.seg * a.nseg : a.ncell, 256, 1u << 16), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -1,23 +1,26 @@
 // arc_mlp.hip -- learned chemistry step on gfx950 MFMA.
 //
-// Network: 5 -> 64 -> 64 -> 2, tanh hidden units, BF16 weights and activations, FP32
+// Network: 8 -> 64 -> 64 -> 2, ReLU hidden units, BF16 weights and activations, FP32
 // accumulation (v_mfma_f32_16x16x32_bf16). Inputs: log10 n_H, x_HI, log10 T, log10 Gamma_HI,
-// log10 dt, standardised. Outputs: the standardised changes x_HI' - x_HI and log10 (T'/T),
-// added to the cell's own FP32 state.
-// Helium is not an input: the gate accepts a cell only when its helium is close to steady.
+// log10 dt, log10 h (photoheating per H atom), x_HeII, x_HeI, standardised. Outputs: the
+// standardised corrections x_HI' - x_base and log10 (T'/T), where x_base relaxes x_HI
+// exponentially towards photoionisation equilibrium with the rates of the start of the step.
+// Helium is not an output: the gate accepts a cell only when its helium is close to steady.
 //
-//   k_infer       per cell: features, MFMA forward, gate; accepted cells are written,
-//                 rejected cells are appended to a list for the plain solver
-//   k_train_grad  quantisation-aware forward and backward of a minibatch (MFMA), one
-//                 gradient partial per wave (summed in fixed order: deterministic)
+//   k_infer       per cell: features, forward pass with the activations kept in registers
+//                 (each layer's MFMA output is the next layer's operand), gate; accepted
+//                 cells are written, rejected cells are appended to a list for the plain solver
+//   k_predict     the same forward pass without the gate (validation, evaluation)
+//   k_train_grad  quantisation-aware forward and backward of a minibatch (MFMA through LDS),
+//                 one gradient partial per wave (summed in fixed order: deterministic)
 //   k_adam        Adam update of the FP32 master parameters
-//   k_publish     BF16 transposed weight images for the MFMA operands
-//   k_predict     forward only, for validation and gate calibration
+//   k_publish     BF16 weight images for the MFMA operands
 #include <hip/hip_runtime.h>
 
 #include <math.h>
 
 #include "arc_chem.h"
+#include "arc_kernels.h"
 #include "arc_mlp.h"
 
 namespace arc {
@@ -60,12 +63,7 @@ __device__ __forceinline__ f32x4 tile_mm(const __bf16* A, int sar, int sak, cons
     return acc;
 }
 
-__device__ __forceinline__ float act(float x)  // tanh
-{
-    const float e = __builtin_amdgcn_exp2f(2.0f * 1.4426950408889634f * fminf(fmaxf(x, -15.0f), 15.0f));
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
-}
-
+__device__ __forceinline__ float act(float x) { return fmaxf(x, 0.0f); }  // ReLU
 
 // Orders one wave's LDS writes before its later reads by other lanes: LDS operations of
 // a wave complete in issue order; the fence keeps the compiler from moving accesses.
@@ -144,74 +142,225 @@ __device__ __forceinline__ void load_model(const Model* m, SharedModel& s)
     if (threadIdx.x < kOut) s.b3[threadIdx.x] = m->b3[threadIdx.x];
 }
 
+
+// ---------------------------------------------------------------------------------
+// Forward pass with the activations in registers.
+//
+// Each layer computes out^T = W in^T as 16x16 tiles: rows (the MFMA M dimension) are output
+// units, columns (N) are 16 cells, the depth (K) runs over the layer's inputs. Lane l = 16q + n
+// receives rows 4q..4q+3 of column n, which are exactly 4 of the 8 depth values that lane must
+// supply as the B operand of the next layer, provided that layer's depth slots are taken in
+// the order perm_k: slot 8q + i of k-step s stands for input unit 32s + 4q + i (i < 4) or
+// 32s + 16 + 4q + i - 4 (i >= 4). The A operands (weights) are loaded in that same order,
+// so no activation leaves the registers.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ int perm_k(int s, int q, int i) { return 32 * s + (i < 4 ? 4 * q + i : 12 + 4 * q + i); }
+
+struct LaneWeights {
+    bf16x8 a1[4];       // layer 1, M-tile t: W1[16t + m][8q + i]
+    bf16x8 a2[4][2];    // layer 2, M-tile t, k-step s: W2[16t + m][perm_k(s, q, i)]
+    bf16x8 a3[2];       // layer 3, k-step s: W3[m][perm_k(s, q, i)] (rows >= kOut are zero)
+    float b1[4][4];     // biases of the rows this lane receives: b[16t + 4q + r]
+    float b2[4][4];
+    float b3[kOut];
+};
+
+__device__ __forceinline__ void load_lane_weights(const Model* M, LaneWeights& w)
+{
+    const int lane = threadIdx.x & 63, m = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w.a1[t][i] = M->w1t[16 * t + m][8 * q + i];
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) w.a2[t][s2][i] = M->w2t[16 * t + m][perm_k(s2, q, i)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            w.b1[t][r] = M->b1[16 * t + 4 * q + r];
+            w.b2[t][r] = M->b2[16 * t + 4 * q + r];
+        }
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w.a3[s2][i] = M->w3t[m][perm_k(s2, q, i)];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) w.b3[k] = M->b3[k];
+}
+
+// Hidden layer: bias, ReLU and BF16 rounding of four M-tiles, packed as the two k-steps of
+// the next layer's B operand.
+__device__ __forceinline__ void hidden_to_operand(const f32x4 d[4], const float b[4][4], bf16x8 h[2])
+{
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            h[s2][r] = (__bf16)act(d[2 * s2][r] + b[2 * s2][r]);
+            h[s2][4 + r] = (__bf16)act(d[2 * s2 + 1][r] + b[2 * s2 + 1][r]);
+        }
+}
+
+// One tile of 16 cells: x = the layer-1 B operand (lanes with q = 0 hold the 8 standardised
+// features of cell n, other lanes zeros). Returns rows 4q..4q+3 of the output tile; lanes
+// with q = 0 hold the two outputs of cell n in elements 0 and 1 (biases included).
+__device__ __forceinline__ f32x4 forward_tile(const LaneWeights& w, bf16x8 x)
+{
+    const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 d[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d[t] = mfma(w.a1[t], x, z);
+    bf16x8 h[2];
+    hidden_to_operand(d, w.b1, h);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d[t] = mfma(w.a2[t][1], h[1], mfma(w.a2[t][0], h[0], z));
+    hidden_to_operand(d, w.b2, h);
+    f32x4 o = mfma(w.a3[1], h[1], mfma(w.a3[0], h[0], z));
+    o[0] += w.b3[0];
+    o[1] += w.b3[1];
+    return o;
+}
+
+// Forward pass of the 64 cells of a wave, one per lane: f = the lane's standardised
+// features; returns the lane's two outputs.
+__device__ __forceinline__ void forward_wave(const LaneWeights& w, const float f[kIn], float& o0, float& o1)
+{
+    const int lane = threadIdx.x & 63, n = lane & 15, q = lane >> 4;
+    // the eight features as four packed BF16 pairs
+    uint32_t pk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const __bf16 lo = (__bf16)f[2 * j];
+        const __bf16 hi = (__bf16)f[2 * j + 1];
+        pk[j] = (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+    }
+    o0 = o1 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        bf16x8 x;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t v = (uint32_t)__shfl((int)pk[j], 16 * c + n, 64);
+            x[2 * j] = __builtin_bit_cast(__bf16, (uint16_t)(q == 0 ? v & 0xFFFFu : 0u));
+            x[2 * j + 1] = __builtin_bit_cast(__bf16, (uint16_t)(q == 0 ? v >> 16 : 0u));
+        }
+        const f32x4 o = forward_tile(w, x);
+        const float v0 = __shfl(o[0], n, 64), v1 = __shfl(o[1], n, 64);
+        if (q == c) {
+            o0 = v0;
+            o1 = v1;
+        }
+    }
+}
+
 __device__ __forceinline__ float safe_log10(float v, float floor_) { return log10f(fmaxf(v, floor_)); }
+
+// Features of a cell: n_H, x_HI, T, Gamma_HI, dt [s], h = photoheating per H atom, x_HeII, x_HeI.
+__device__ __forceinline__ void cell_features(float nh, float x, float T, float gam, float ldt, float h, float xheii,
+                                              float xhei, float f[kIn])
+{
+    static_assert(kIn == 8, "eight features fill the first MFMA depth group");
+    f[0] = log10f(nh);
+    f[1] = x;
+    f[2] = log10f(T);
+    f[3] = safe_log10(gam, kGammaFloor);
+    f[4] = ldt;
+    f[5] = safe_log10(h, kHeatFloor);
+    f[6] = xheii;
+    f[7] = xhei;
+}
+
+// Baseline of x_HI': dx/dt = a (1 - x) - b x with a = alpha_HII(T) n_e and b = Gamma_HI +
+// k_HI(T) n_e held at their start-of-step values (section 2.7 rates), solved exactly:
+// x_base = x_eq + (x - x_eq) exp(-(a + b) dt), x_eq = a / (a + b).
+__device__ __forceinline__ float x_baseline(float nh, float x, float T, float gam, float xheii, float xhei, float dt,
+                                            float y, int collisional)
+{
+    const chem::Coef k = chem::coefficients(T);
+    const float xheiii = fmaxf(0.0f, 1.0f - xhei - xheii);
+    const float ne = nh * ((1.0f - x) + y * (xheii + 2.0f * xheiii));
+    const float a = k.a_hii * ne;
+    const float b = gam + (collisional ? k.k_hi * ne : 0.0f);
+    const float lam = a + b;
+    if (!(lam > 0.0f)) return x;
+    const float xeq = a / lam;
+    return xeq + (x - xeq) * expf(-lam * dt);
+}
+
+__device__ __forceinline__ void standardise(const Model* M, bool valid, float f[kIn])
+{
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) f[k] = valid ? (f[k] - M->in_mu[k]) / M->in_sd[k] : 0.0f;
+}
 
 // ---------------------------------------------------------------------------------
 // Inference with the gate.
 // ---------------------------------------------------------------------------------
-constexpr int kInferWaves = 4;
-
-__global__ __launch_bounds__(64 * kInferWaves) void k_infer(InferArgs a)
+__global__ __launch_bounds__(256) void k_infer(InferArgs a)
 {
-    __shared__ SharedModel sm;
-    __shared__ __bf16 xs[kInferWaves][64 * kK1];
-    __shared__ __bf16 hs[kInferWaves][64 * kHid];
-    __shared__ float os[kInferWaves][64 * kOut];
     const Model* M = a.model;
-    load_model(M, sm);
-    __syncthreads();
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    LaneWeights w;
+    load_lane_weights(M, w);
+    const int lane = threadIdx.x & 63;
     const uint64_t lt = __lanemask_lt();
-    const float ldt = log10f((float)a.dt);
+    const float dtf = (float)a.dt, ldt = log10f(dtf);
+    const float yf = (float)a.y;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x + 64 * wid; base < a.ncell; base += stride) {
+    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < a.ncell; base += stride) {
         const uint32_t c = base + lane;
         const bool valid = c < a.ncell;
-        float f[kIn] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        float nh = 1.0f, T = 1.0f, x0 = 0.0f;
+        float nh = 1.0f, T = 1.0f, x0 = 0.0f, xhei = 0.0f, xheii = 0.0f, gam = 0.0f, h = 0.0f, xb = 0.0f;
         if (valid) {
             nh = a.n_h[c];
             T = a.temp[c];
             x0 = a.x_hi[c];
-            f[0] = log10f(nh);
-            f[1] = x0;
-            f[2] = log10f(T);
-            f[3] = safe_log10(a.gamma[c], kGammaFloor);
-            f[4] = ldt;
+            xhei = a.x_hei[c];
+            xheii = a.x_heii[c];
+            gam = a.gamma[c];
+            h = a.heat[c] * x0 + yf * (a.heat[(size_t)a.ncell + c] * xhei + a.heat[2 * (size_t)a.ncell + c] * xheii);
         }
-        __bf16* X = xs[wid];
+        float f[kIn];
+        cell_features(nh, x0, T, gam, ldt, h, xheii, xhei, f);
+        float raw[kGateDims];
 #pragma unroll
-        for (int k = 0; k < kK1; ++k)
-            X[lane * kK1 + k] = (__bf16)(k < kIn && valid ? (f[k] - M->in_mu[k]) / M->in_sd[k] : 0.0f);
-        wave_sync();
-        forward64(X, hs[wid], nullptr, os[wid], sm.w1t, sm.w2t, sm.w3t, sm.b1, sm.b2, sm.b3);
+        for (int k = 0; k < kGateDims; ++k) raw[k] = f[k];
+        standardise(M, valid, f);
+        float o0, o1;
+        forward_wave(w, f, o0, o1);
         bool accept = false;
         float xn = 0.0f, Tn = 0.0f;
         if (valid) {
-            const float o0 = os[wid][lane * kOut], o1 = os[wid][lane * kOut + 1];
-            xn = fminf(fmaxf(x0 + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
-            Tn = T * exp10f(o1 * M->out_sd[1] + M->out_mu[1]);
             accept = true;
             if (a.gated) {
                 // (1) inside the training range, in a bin with enough samples and a small
                 //     held-out error
                 uint32_t bin = 0;
 #pragma unroll
-                for (int k = kIn - 1; k >= 0; --k) {
-                    const float u = (f[k] - M->lo[k]) / (M->hi[k] - M->lo[k]);
+                for (int k = kGateDims - 1; k >= 0; --k) {
+                    const float u = (raw[k] - M->lo[k]) / (M->hi[k] - M->lo[k]);
                     accept = accept && u >= 0.0f && u <= 1.0f;
                     const int b = min(kGate - 1, max(0, (int)(u * kGate)));
                     bin = bin * kGate + (uint32_t)b;
                 }
                 accept = accept && M->gate_count[bin] >= a.gate_min_count && M->gate_err[bin] <= a.gate_tol;
-                // (2) physical outputs
+            }
+            // the outputs (the baseline only where they can still be used)
+            if (accept) {
+                xb = x_baseline(nh, x0, T, gam, xheii, xhei, dtf, M->base_y, M->base_collisional);
+                xn = fminf(fmaxf(xb + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
+                Tn = T * exp10f(o1 * M->out_sd[1] + M->out_mu[1]);
+            }
+            if (a.gated) {
+                // (2) physical output temperature
                 accept = accept && Tn >= a.t_floor && Tn < 1e9f;
-                // (3) helium close to steady over dt (the network does not see helium)
+                // (3) helium close to steady over dt (the network does not predict helium)
                 if (accept && a.y > 0.0) {
                     const double nhd = nh, nhe = a.y * nhd;
-                    const double nhei = nhe * a.x_hei[c], nheii = nhe * a.x_heii[c];
+                    const double nhei = nhe * xhei, nheii = nhe * xheii;
                     const double nheiii = fmax(0.0, nhe - nhei - nheii);
-                    const double nhii = nhd * (1.0 - a.x_hi[c]);
+                    const double nhii = nhd * (1.0 - x0);
                     const double ne = nhii + nheii + 2.0 * nheiii;
                     const chem::Coef k = chem::coefficients(T);
                     const double kc = a.collisional ? 1.0 : 0.0;
@@ -227,23 +376,26 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_infer(InferArgs a)
             a.x_hi[c] = xn;
             a.temp[c] = Tn;
         }
+        // rejected cells join the list segment of this tile (one atomic per wave, on a
+        // counter shared by 1 / kListSegs of the tiles)
         const uint64_t rej = __ballot(valid && !accept);
         if (rej) {
             const int leader = __ffsll((unsigned long long)rej) - 1;
+            const uint32_t j = (base >> 6) & (kListSegs - 1);
             uint32_t w0 = 0;
-            if (lane == leader) w0 = atomicAdd(a.n_fallback, (uint32_t)__popcll(rej));
+            if (lane == leader) w0 = atomicAdd(a.seg_counts + 16 * j, (uint32_t)__popcll(rej));
             w0 = __shfl(w0, leader, 64);
-            if (valid && !accept) a.fallback[w0 + (uint32_t)__popcll(rej & lt)] = c;
+            if (valid && !accept) a.fallback[(size_t)j * a.seg + w0 + (uint32_t)__popcll(rej & lt)] = c;
         }
     }
 }
 
 hipError_t launch_infer(const InferArgs& a, hipStream_t s)
 {
-    size_t blocks = (a.ncell + 64 * kInferWaves - 1) / (64 * kInferWaves);
-    if (blocks > 8192) blocks = 8192;
+    size_t blocks = (a.ncell + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    k_infer<<<(unsigned)blocks, 64 * kInferWaves, 0, s>>>(a);
+    k_infer<<<(unsigned)blocks, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -252,37 +404,35 @@ hipError_t launch_infer(const InferArgs& a, hipStream_t s)
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ void raw_features(const float* x, float f[kIn])
 {
-    f[0] = log10f(x[0]);
-    f[1] = x[1];
-    f[2] = log10f(x[2]);
-    f[3] = safe_log10(x[3], kGammaFloor);
-    f[4] = log10f(x[4]);
+    cell_features(x[0], x[1], x[2], x[3], log10f(x[4]), x[5], x[6], x[7], f);
 }
 
-__global__ __launch_bounds__(64 * kInferWaves) void k_predict(const Model* M, const float* X, const uint32_t* idx,
-                                                              uint32_t m, float* P)
+__device__ __forceinline__ float raw_baseline(const float* x, float y, int collisional)
 {
-    __shared__ SharedModel sm;
-    __shared__ __bf16 xs[kInferWaves][64 * kK1];
-    __shared__ __bf16 hs[kInferWaves][64 * kHid];
-    __shared__ float os[kInferWaves][64 * kOut];
-    load_model(M, sm);
-    __syncthreads();
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (uint32_t base = blockIdx.x * blockDim.x + 64 * wid; base < m; base += gridDim.x * blockDim.x) {
+    return x_baseline(x[0], x[1], x[2], x[3], x[6], x[7], x[4], y, collisional);
+}
+
+__global__ __launch_bounds__(256) void k_predict(const Model* M, const float* X, const uint32_t* idx, uint32_t m,
+                                                 float* P)
+{
+    LaneWeights w;
+    load_lane_weights(M, w);
+    const int lane = threadIdx.x & 63;
+    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + lane;
         const bool valid = i < m;
-        float f[kIn] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        const float* x = X + (size_t)(valid ? (idx ? idx[i] : i) : 0u) * 5;
-        if (valid) raw_features(x, f);
-#pragma unroll
-        for (int k = 0; k < kK1; ++k)
-            xs[wid][lane * kK1 + k] = (__bf16)(k < kIn && valid ? (f[k] - M->in_mu[k]) / M->in_sd[k] : 0.0f);
-        wave_sync();
-        forward64(xs[wid], hs[wid], nullptr, os[wid], sm.w1t, sm.w2t, sm.w3t, sm.b1, sm.b2, sm.b3);
+        const float* x = X + (size_t)(valid ? (idx ? idx[i] : i) : 0u) * kIn;
+        float f[kIn] = {1.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float xb = 0.0f;
         if (valid) {
-            const float o0 = os[wid][lane * kOut], o1 = os[wid][lane * kOut + 1];
-            P[(size_t)i * 2] = fminf(fmaxf(x[1] + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
+            raw_features(x, f);
+            xb = raw_baseline(x, M->base_y, M->base_collisional);
+        }
+        standardise(M, valid, f);
+        float o0, o1;
+        forward_wave(w, f, o0, o1);
+        if (valid) {
+            P[(size_t)i * 2] = fminf(fmaxf(xb + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
             P[(size_t)i * 2 + 1] = x[2] * exp10f(o1 * M->out_sd[1] + M->out_mu[1]);
         }
     }
@@ -291,32 +441,33 @@ __global__ __launch_bounds__(64 * kInferWaves) void k_predict(const Model* M, co
 hipError_t launch_predict(const Model* model, const float* X, const uint32_t* idx, uint32_t m, float* P,
                           hipStream_t s)
 {
-    size_t blocks = (m + 64 * kInferWaves - 1) / (64 * kInferWaves);
-    if (blocks > 8192) blocks = 8192;
+    size_t blocks = (m + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    k_predict<<<(unsigned)blocks, 64 * kInferWaves, 0, s>>>(model, X, idx, m, P);
+    k_predict<<<(unsigned)blocks, 256, 0, s>>>(model, X, idx, m, P);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
-// Features and targets of raw samples (n_H, x_HI, T, Gamma_HI, dt) and (x_HI', T').
+// Features and targets of raw samples X [m][kIn] and (x_HI', T').
 // ---------------------------------------------------------------------------------
-__global__ void k_features(const float* X, const float* Y, uint32_t m, float* F, float* Yt)
+__global__ void k_features(const float* X, const float* Y, uint32_t m, float y, int collisional, float* F, float* Yt)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
-        const float* x = X + (size_t)i * 5;
+        const float* x = X + (size_t)i * kIn;
         raw_features(x, F + (size_t)i * kIn);
-        Yt[(size_t)i * 2] = Y[(size_t)i * 2] - x[1];
+        Yt[(size_t)i * 2] = Y[(size_t)i * 2] - raw_baseline(x, y, collisional);
         Yt[(size_t)i * 2 + 1] = log10f(Y[(size_t)i * 2 + 1]) - log10f(x[2]);
     }
 }
 
-hipError_t launch_features(const float* X, const float* Y, uint32_t m, float* F, float* Yt, hipStream_t s)
+hipError_t launch_features(const float* X, const float* Y, uint32_t m, float y, int collisional, float* F, float* Yt,
+                           hipStream_t s)
 {
     size_t blocks = (m + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    k_features<<<(unsigned)blocks, 256, 0, s>>>(X, Y, m, F, Yt);
+    k_features<<<(unsigned)blocks, 256, 0, s>>>(X, Y, m, y, collisional, F, Yt);
     return hipGetLastError();
 }
 
@@ -371,7 +522,7 @@ __global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) P[kW3 + (16 * t + 4 * q + r) * kOut + r16] = d[r];
     }
-    // dz2 = (dO W3^T) * (1 - H2^2)             (M = 64 s, N = 64 k, K = 32 n)
+    // dz2 = (dO W3^T) * [H2 > 0]               (M = 64 s, N = 64 k, K = 32 n)
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
@@ -380,7 +531,7 @@ __global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * t + 4 * q + r, col = 16 * nt + r16;
                 const float h = (float)H[row * kHid + col];
-                D2[row * kHid + col] = (__bf16)(d[r] * (1.0f - h * h));
+                D2[row * kHid + col] = (__bf16)(h > 0.0f ? d[r] : 0.0f);
             }
         }
     wave_sync();
@@ -392,7 +543,7 @@ __global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
 #pragma unroll
             for (int r = 0; r < 4; ++r) P[kW2 + (16 * t + 4 * q + r) * kHid + 16 * nt + r16] = d[r];
         }
-    // dz1 = (dz2 W2^T) * (1 - H1^2)            (M = 64 s, N = 64 k, K = 64 n)
+    // dz1 = (dz2 W2^T) * [H1 > 0]              (M = 64 s, N = 64 k, K = 64 n)
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
@@ -401,7 +552,7 @@ __global__ __launch_bounds__(64) void k_train_grad(TrainArgs a)
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * t + 4 * q + r, col = 16 * nt + r16;
                 const float h = (float)H1[row * kHid + col];
-                D1[row * kHid + col] = (__bf16)(d[r] * (1.0f - h * h));
+                D1[row * kHid + col] = (__bf16)(h > 0.0f ? d[r] : 0.0f);
             }
         }
     wave_sync();

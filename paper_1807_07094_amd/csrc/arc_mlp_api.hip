@@ -20,7 +20,12 @@ using namespace arc::mlp;
 namespace {
 
 constexpr uint32_t kMagic = 0x41524d31u;  // "ARM1"
-constexpr uint32_t kVersion = 2;           // residual outputs
+constexpr uint32_t kVersion = 4;           // eight features, ReLU, corrections of an x_HI baseline
+// Gate calibration: a bin's error is kGateSafety times the largest held-out error in it
+// (the held-out maximum of a few dozen samples underestimates the bin's true maximum), with
+// the relative temperature error counted against kTempTol times the fraction tolerance.
+constexpr float kGateSafety = 2.0f;
+constexpr double kTempTol = 10.0;
 
 struct Blob {
     uint32_t magic, version, nparams, pad;
@@ -45,7 +50,7 @@ hipError_t ensure_bytes(void** p, size_t* cap, size_t need)
 int gate_bin(const float* f, const float* lo, const float* hi)
 {
     int bin = 0;
-    for (int k = kIn - 1; k >= 0; --k) {
+    for (int k = kGateDims - 1; k >= 0; --k) {
         const float u = (f[k] - lo[k]) / (hi[k] - lo[k]);
         const int b = std::min(kGate - 1, std::max(0, (int)(u * kGate)));
         bin = bin * kGate + b;
@@ -125,7 +130,8 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
     guard.ptrs.push_back(F);
     TRY(hipMalloc((void**)&Yt, (size_t)m * 2 * sizeof(float)));
     guard.ptrs.push_back(Yt);
-    TRY(launch_features(X, Y, (uint32_t)m, F, Yt, st));
+    if (!(p->y_he >= 0) || !std::isfinite(p->y_he)) return arc::ctx_fail(ctx, ARC_E_RANGE, "y_he must be >= 0");
+    TRY(launch_features(X, Y, (uint32_t)m, (float)p->y_he, p->collisional ? 1 : 0, F, Yt, st));
     std::vector<float> hF((size_t)m * kIn), hY((size_t)m * 2);
     TRY(hipMemcpyAsync(hF.data(), F, hF.size() * sizeof(float), hipMemcpyDeviceToHost, st));
     TRY(hipMemcpyAsync(hY.data(), Yt, hY.size() * sizeof(float), hipMemcpyDeviceToHost, st));
@@ -146,6 +152,8 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
 
     Model hm;
     std::memset(&hm, 0, sizeof hm);
+    hm.base_y = (float)p->y_he;
+    hm.base_collisional = p->collisional ? 1 : 0;
     for (int k = 0; k < kIn; ++k) {
         double s = 0, s2 = 0;
         float lo = INFINITY, hi = -INFINITY;
@@ -232,7 +240,7 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
     }
 
     // held-out predictions (the inference arithmetic, from the raw samples), errors and
-    // the gate calibration: per bin the largest of |x_HI' error| and |T' error| / T'
+    // the gate calibration
     std::vector<float> rY((size_t)m * 2);
     TRY(hipMemcpyAsync(rY.data(), Y, rY.size() * sizeof(float), hipMemcpyDeviceToHost, st));
     uint32_t* dval = nullptr;
@@ -253,10 +261,11 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
         const double dl = std::log10((double)hP[2 * j + 1] / (double)rY[(size_t)i * 2 + 1]);
         se_x += ex * ex;
         se_t += dl * dl;
-        const float e = (float)std::max(ex, et);
+        // one error per sample: the x_HI' error, or the relative T' error over kTempTol
+        const float e = (float)std::max(ex, et / kTempTol);
         emax = std::max(emax, (double)e);
         const int b = gate_bin(&hF[(size_t)i * kIn], hm.lo, hm.hi);
-        hm.gate_err[b] = std::max(hm.gate_err[b], e);
+        hm.gate_err[b] = std::max(hm.gate_err[b], kGateSafety * e);
     }
     // bins without held-out samples stay closed
     {

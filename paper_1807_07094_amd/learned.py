@@ -19,7 +19,8 @@ def sample_states(ctx, arc_mod, w: W.Workload, n: int, seed: int, steps: int = 3
                   dt_range_myr=(1e-3, 10.0)):
     """Draw n (inputs, targets) pairs from the states of workload w over `steps` RT steps.
 
-    Returns device tensors X [n, 5] = (n_H, x_HI, T, Gamma_HI, dt) and Y [n, 2] = (x_HI', T')."""
+    Returns device tensors X [n, 8] = (n_H, x_HI, T, Gamma_HI, dt, h, x_HeII, x_HeI), with h
+    the photoheating per H atom, and Y [n, 2] = (x_HI', T')."""
     import torch
 
     rng = np.random.Generator(np.random.Philox(key=int(seed) | (7 << 64)))
@@ -65,7 +66,10 @@ def sample_states(ctx, arc_mod, w: W.Workload, n: int, seed: int, steps: int = 3
             for k in ("x_hi", "x_hei", "x_heii", "temp"):
                 out[k][keep] = sub[k].reshape(-1)[: sel.size]
         dt_col = torch.from_numpy(dts[which].astype(np.float32)).cuda()
-        xs.append(torch.stack([flat["n_h"], flat["x_hi"], flat["temp"], gam[0], dt_col], dim=1))
+        y = float(w.grid["y_he"])
+        h = hea[0] * flat["x_hi"] + y * (hea[1] * flat["x_hei"] + hea[2] * flat["x_heii"])
+        xs.append(torch.stack([flat["n_h"], flat["x_hi"], flat["temp"], gam[0], dt_col, h, flat["x_heii"],
+                               flat["x_hei"]], dim=1))
         ys.append(torch.stack([out["x_hi"], out["temp"]], dim=1))
         # advance the run itself by one RT step so that later samples see evolved states
         ctx.chem_step(g, gamma, heat, w.dt, **w.chem)

@@ -16,7 +16,7 @@ from paper_1807_07094_amd import workload as W
 
 pytestmark = pytest.mark.gpu
 
-HID, K1, OUTP = 64, 32, 16
+HID, K1, OUTP, NIN = 64, 32, 16, 8
 
 
 @pytest.fixture(scope="module")
@@ -28,9 +28,9 @@ def ctx(arc):
 
 @pytest.fixture(scope="module")
 def trained(arc, ctx):
-    X, Y = learned.training_set(ctx, arc, n=120_000, seed=5, sizes=(48, 64), n_src=(32, 48))
+    X, Y = learned.training_set(ctx, arc, n=400_000, seed=5, sizes=(48, 64), n_src=(32, 48))
     net = arc.MLP(ctx)
-    rep = net.train(X, Y, epochs=20, batch=1024, lr=2e-3, seed=3)
+    rep = net.train(X, Y, epochs=10, batch=1024, lr=2e-3, seed=3)
     return net, rep, X, Y
 
 
@@ -50,11 +50,12 @@ def parse_model(blob: bytes):
     off = 16  # magic, version, nparams, pad
     f = lambda n: (np.frombuffer(blob, np.float32, n, off), n * 4)
     out = {}
-    for name, n in (("in_mu", 5), ("in_sd", 5), ("lo", 5), ("hi", 5), ("out_mu", 2), ("out_sd", 2), ("b1", HID),
-                    ("b2", HID), ("b3", 2)):
+    for name, n in (("in_mu", NIN), ("in_sd", NIN), ("lo", NIN), ("hi", NIN), ("out_mu", 2), ("out_sd", 2),
+                    ("base_y", 1), ("base_coll", 1), ("b1", HID), ("b2", HID), ("b3", 2)):
         a, nb = f(n)
         out[name] = a.copy()
         off += nb
+    out["base_coll"] = out["base_coll"].view(np.int32)
     for name, shape in (("w1t", (HID, K1)), ("w2t", (HID, HID)), ("w3t", (OUTP, HID))):
         n = shape[0] * shape[1]
         out[name] = bf16_to_f32(np.frombuffer(blob, np.uint16, n, off)).reshape(shape)
@@ -62,17 +63,38 @@ def parse_model(blob: bytes):
     return out
 
 
+def x_baseline(m, X):
+    """The network's x_HI baseline in FP32: exact relaxation with the start-of-step recombination
+    (case-B fit), collisional and photoionisation rates (Hui & Gnedin 1997 fits)."""
+    f32 = np.float32
+    nh, x, T, gam, dt, xheii, xhei = (X[:, i].astype(f32) for i in (0, 1, 2, 3, 4, 6, 7))
+    lhi = f32(2.0 * 157807.0) / T
+    a_hii = f32(2.753e-14) * lhi ** f32(1.5) / (f32(1) + (lhi / f32(2.740)) ** f32(0.407)) ** f32(2.242)
+    k_hi = (f32(21.11) * T ** f32(-1.5) * np.exp(-lhi / f32(2)) * lhi ** f32(-1.089)
+            / (f32(1) + (lhi / f32(0.354)) ** f32(0.874)) ** f32(1.101))
+    y = m["base_y"][0]
+    ne = nh * ((f32(1) - x) + y * (xheii + f32(2) * np.maximum(f32(0), f32(1) - xhei - xheii)))
+    a = a_hii * ne
+    b = gam + (k_hi * ne if m["base_coll"][0] else f32(0))
+    lam = a + b
+    with np.errstate(divide="ignore", invalid="ignore"):
+        xeq = a / lam
+        xb = xeq + (x - xeq) * np.exp(-lam * dt)
+    return np.where(lam > 0, xb, x).astype(f32)
+
+
 def reference_forward(m, X):
     """NumPy forward pass in the network's arithmetic: BF16 inputs, weights and hidden
-    activations, FP32 sums; outputs are changes added to the sample's own x_HI and log10 T.
-    Returns (x_HI', log10 T')."""
+    activations (ReLU), FP32 sums; outputs are corrections of the x_HI baseline and the change
+    of log10 T. Returns (x_HI', log10 T')."""
     f = np.stack([np.log10(X[:, 0]), X[:, 1], np.log10(X[:, 2]), np.log10(np.maximum(X[:, 3], 1e-30)),
-                  np.log10(X[:, 4])], axis=1).astype(np.float32)
+                  np.log10(X[:, 4]), np.log10(np.maximum(X[:, 5], 1e-40)), X[:, 6], X[:, 7]],
+                 axis=1).astype(np.float32)
     x = f32_to_bf16((f - m["in_mu"]) / m["in_sd"])
-    h1 = f32_to_bf16(np.tanh(x @ m["w1t"][:, :5].T + m["b1"]))
-    h2 = f32_to_bf16(np.tanh(h1 @ m["w2t"].T + m["b2"]))
+    h1 = f32_to_bf16(np.maximum(x @ m["w1t"][:, :NIN].T + m["b1"], 0.0))
+    h2 = f32_to_bf16(np.maximum(h1 @ m["w2t"].T + m["b2"], 0.0))
     o = h2 @ m["w3t"][:2].T + m["b3"]
-    x_new = np.clip(X[:, 1] + (o[:, 0] * m["out_sd"][0] + m["out_mu"][0]), 0.0, 1.0)
+    x_new = np.clip(x_baseline(m, X) + (o[:, 0] * m["out_sd"][0] + m["out_mu"][0]), 0.0, 1.0)
     return x_new, np.log10(X[:, 2]) + (o[:, 1] * m["out_sd"][1] + m["out_mu"][1])
 
 
@@ -136,6 +158,7 @@ def test_gated_step_within_tolerance_of_plain(arc, ctx, trained):
     dx = (gated["x_hi"] - plain["x_hi"]).abs()
     dt = ((gated["temp"] - plain["temp"]) / plain["temp"]).abs()
     # judge run: the plain solver on every cell; the accepted cells stay within the gate
+    # (fractions to gate_tol absolute, temperature to 10 gate_tol relative)
     assert float(dx.max()) <= 1e-3
     assert float(dt.max()) <= 1e-2
     # helium is untouched by the network and equal to the plain solver where it fell back
