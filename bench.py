@@ -68,7 +68,8 @@ def main():
     ap.add_argument("--tune-blocks", type=int, default=0)
     ap.add_argument("--tune-refill", type=int, default=0)
     ap.add_argument("--tune-item-level", type=int, default=0)
-    ap.add_argument("--tuned", action="store_true", help="autotuned launch shape (tuned before warm-up)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="default launch shape instead of the autotuned one (tuned before warm-up)")
     ap.add_argument("--graph", type=int, default=1, help="1: replay the trace's recorded HIP graphs")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only copy this many GiB device to device (calibrates HBM byte counters) and exit")
@@ -139,7 +140,7 @@ def main():
 
     schedule = args.schedule
     tune_info = None
-    if args.tuned and args.schedule == "batched":
+    if not args.no_tune and args.schedule == "batched" and not any(tune.values()):
         nsrc_all = len(w.sources["ndot"])
         sub = w.subset(np.arange(0, nsrc_all, max(1, nsrc_all // 256)))
         tt = time.perf_counter()

@@ -113,7 +113,8 @@ typedef struct {
     int32_t tune_refill;   /* batched: refill a wave once this many lanes idle (0 = default) */
     int32_t tune_item_level; /* batched: HEALPix level whose rays become the persistent
                                 launch's work items; earlier levels are traced level by
-                                level (0 = first level with 16 items per wave) */
+                                level (0 = two levels below the first level with 16 items
+                                per wave) */
     uint64_t* tree_out;    /* optional device array: every ray traced is appended as
                               (src << 32) | (level << 28) | pixel; NULL = off */
     int64_t tree_cap;      /* capacity of tree_out in entries */
@@ -159,7 +160,8 @@ typedef struct {
     int32_t waves;         /* waves per workgroup of the persistent launch (1, 2, 4, 8) */
     int32_t waves_per_cu;  /* resident waves per compute unit the grid is sized for */
     int32_t refill;        /* refill a wave once this many lanes idle */
-    int32_t item_delta;    /* work-item level relative to the automatic choice */
+    int32_t item_delta;    /* work-item level minus the first level with >= 16 items per wave
+                              (ARC_SCHED_BATCHED uses 2) */
     double ms_best;        /* trace time of the chosen shape [ms] (tuning sources) */
     double ms_default;     /* trace time of the default shape [ms] (tuning sources) */
     int32_t candidates;    /* shapes timed */
@@ -168,7 +170,7 @@ typedef struct {
 /* Autotuner of the batched schedule (no paper counterpart: the paper traces one source
  * at a time). Times launch shapes of the batched tracer on the given sources (pass a
  * representative subset: every shape traces them all, twice) by coordinate descent over
- * waves per workgroup and per CU, the refill threshold and the work-item level. Every
+ * the work-item level, waves per workgroup and per CU, and the refill threshold. Every
  * shape's fixed-point field is checked against the first one's bit for bit (two 64-bit
  * checksums); a difference returns ARC_E_MISMATCH. The best shape is cached in the context
  * for this grid size, bin count, level range and precision, where ARC_SCHED_BATCHED_TUNED

@@ -439,14 +439,18 @@ __device__ __forceinline__ int deposit_seg(const TraceArgs& A, Ray<NB>& ray, con
 // Segments whose geometry is computed ahead of their deposits (opacity loads in flight
 // per lane).
 #ifndef ARC_SEG_AHEAD
-#define ARC_SEG_AHEAD 4
+#define ARC_SEG_AHEAD 8
 #endif
 constexpr int kSegAhead = ARC_SEG_AHEAD;
+#ifndef ARC_DEP_WINDOW
+#define ARC_DEP_WINDOW 2
+#endif
+constexpr int kDepWindow = ARC_DEP_WINDOW;  // segments of each lane whose deposits are merged together
 
 // Up to K crossings of one lane per pass: the geometry of K segments is computed first
 // and their opacities are loaded together (K loads in flight per lane), then the
-// segments are deposited in order; `deposit.add` is called K times by the whole wave, then
-// `deposit.flush` once.
+// segments are deposited in order; `deposit.add` is called once per kDepWindow segments by
+// the whole wave, then `deposit.flush` once.
 // Returns the lane's final event of the pass (kContinue if the ray goes on).
 template <int NB, int PREC, int K, class Depositor>
 __device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool active, LaneStats& st,
@@ -469,10 +473,14 @@ __device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool
         if (have[j]) kappa_at<NB>(A, sg[j].cell, kap[j]);
     int ev = kContinue;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        Dep<NB> dep;
-        dep.cell = kNoCell;
-        if (have[j] && ev == kContinue) ev = deposit_seg<NB, PREC>(A, ray, sg[j], kap[j], st, dep);
+    for (int j0 = 0; j0 < K; j0 += kDepWindow) {
+        Dep<NB> dep[kDepWindow];
+#pragma unroll
+        for (int w = 0; w < kDepWindow; ++w) {
+            const int j = j0 + w;
+            dep[w].cell = kNoCell;
+            if (j < K && have[j] && ev == kContinue) ev = deposit_seg<NB, PREC>(A, ray, sg[j], kap[j], st, dep[w]);
+        }
         deposit.add(dep);
     }
     deposit.flush();
@@ -511,23 +519,25 @@ __device__ __forceinline__ StackRec<NB> child_stack(const Ray<NB>& ray, int k)
     return r;
 }
 
-// Fixed-point deposition of one crossing per lane, called by all 64 lanes together.
-// Atomic adds cost per distinct cache line an instruction touches, so the NB bins of a
-// lane's cell are issued by NB adjacent lanes of the same instruction: instruction k,
-// lane j adds bin (64k + j) mod NB of crossing (64k + j) / NB.
+// Fixed-point deposition, called by all 64 lanes together. Atomic adds cost per distinct
+// cache line an instruction touches, so the NB bins of a cell are issued by NB adjacent
+// lanes of the same instruction: instruction k, lane j adds bin (64k + j) mod NB of item
+// (64k + j) / NB.
 #ifndef ARC_DEDUP
 #define ARC_DEDUP 1  // 0: every lane's crossing deposited on its own
 #endif
-constexpr int kDepSlots = 128;  // hash slots per wave, power of two
+constexpr int kDepSlots = 128 * kDepWindow;  // hash slots per wave
+constexpr int kDepShift = kDepWindow == 1 ? 32 - 7 : (kDepWindow == 2 ? 32 - 8 : 32 - 9);
+static_assert(kDepWindow == 1 || kDepWindow == 2 || kDepWindow == 4, "window of 1, 2 or 4 segments");
 
-// Per-wave LDS space of the deduplicating deposit.
+// Per-wave LDS space of the deduplicating deposit (item ids and ranks fit in a byte).
 template <int NB>
 struct DepScratch {
     uint32_t slot_cell[kDepSlots];
-    uint32_t slot_lane[kDepSlots];
-    uint32_t slot_rank[kDepSlots];
-    uint32_t cell[64];
-    unsigned long long q[64][NB];
+    uint8_t slot_id[kDepSlots];
+    uint8_t slot_rank[kDepSlots];
+    uint32_t cell[64 * kDepWindow];
+    unsigned long long q[64 * kDepWindow][NB];
 };
 
 template <int NB>
@@ -554,44 +564,70 @@ __device__ __forceinline__ void deposit_wave_plain(const TraceArgs& A, const Dep
     }
 }
 
-// Crossings of the same cell by several lanes are first summed in LDS, so that each
-// distinct cell costs one set of atomics (integer sums: the result is bitwise the same).
-// Lanes hash their cell into a per-wave table; lanes whose cell owns its slot add into
-// the slot's entry, lanes that lost their slot to another cell go alone. LDS operations
-// of one wave complete in issue order, and the racy table accesses are volatile so that
-// each read really observes the wave's writes.
+// Crossings of the same cell, by several lanes and over the kDepWindow segments each lane
+// brings, are first summed in LDS, so that each distinct cell costs one set of atomics
+// (integer sums: the result is bitwise the same). Items hash their cell into a per-wave
+// table; items whose cell owns its slot add into the slot's entry, items whose slot was
+// taken by another cell go alone. LDS operations of one wave complete in issue order, and
+// the racy table accesses are volatile so that each read really observes the wave's writes.
 template <int NB>
-__device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep<NB>& d, DepScratch<NB>* S)
+__device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep<NB> (&d)[kDepWindow],
+                                                   DepScratch<NB>* S)
 {
+    constexpr int W = kDepWindow;
     volatile uint32_t* slot_cell = S->slot_cell;
-    volatile uint32_t* slot_lane = S->slot_lane;
-    volatile uint32_t* slot_rank = S->slot_rank;
+    volatile uint8_t* slot_id = S->slot_id;
+    volatile uint8_t* slot_rank = S->slot_rank;
     volatile uint32_t* st_cell = S->cell;
     const int lane = threadIdx.x & 63;
-    const bool v = d.cell != kNoCell;
-    const uint32_t h = (d.cell * 2654435761u) >> (32 - 7);
-    static_assert(kDepSlots == 128, "hash width");
-    if (v) slot_cell[h] = d.cell;
-    const bool in = v && slot_cell[h] == d.cell;
-    if (in) slot_lane[h] = (uint32_t)lane;
-    const bool lead = in && slot_lane[h] == (uint32_t)lane;
-    const bool emit = lead || (v && !in);
-    const uint64_t em = __ballot(emit);
-    const int n = __popcll(em);
+    const uint64_t lt = __lanemask_lt();
+    bool v[W], in[W], lead[W];
+    uint32_t h[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        v[w] = d[w].cell != kNoCell;
+        h[w] = (d[w].cell * 2654435761u) >> kDepShift;
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        if (v[w]) slot_cell[h[w]] = d[w].cell;
+#pragma unroll
+    for (int w = 0; w < W; ++w) in[w] = v[w] && slot_cell[h[w]] == d[w].cell;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        if (in[w]) slot_id[h[w]] = (uint8_t)(64 * w + lane);
+#pragma unroll
+    for (int w = 0; w < W; ++w) lead[w] = in[w] && slot_id[h[w]] == (uint8_t)(64 * w + lane);
+    int rank[W];
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const bool emit = lead[w] || (v[w] && !in[w]);
+        const uint64_t em = __ballot(emit);
+        rank[w] = emit ? n + __popcll(em & lt) : -1;
+        n += __popcll(em);
+    }
     if (n == 0) return;
-    const int rank = __popcll(em & __lanemask_lt());
-    if (lead) slot_rank[h] = (uint32_t)rank;
-    if (emit) {
-        st_cell[rank] = d.cell;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) *(volatile unsigned long long*)&S->q[rank][b] = (unsigned long long)d.q[b];
-    }
-    if (in && !lead) {
-        const uint32_t r = slot_rank[h];
+    for (int w = 0; w < W; ++w)
+        if (lead[w]) slot_rank[h[w]] = (uint8_t)rank[w];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            if (d.q[b] != 0) atomicAdd(&S->q[r][b], (unsigned long long)d.q[b]);
-    }
+    for (int w = 0; w < W; ++w)
+        if (rank[w] >= 0) {
+            st_cell[rank[w]] = d[w].cell;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                *(volatile unsigned long long*)&S->q[rank[w]][b] = (unsigned long long)d[w].q[b];
+        }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        if (in[w] && !lead[w]) {
+            const uint32_t r = slot_rank[h[w]];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (d[w].q[b] != 0) atomicAdd(&S->q[r][b], (unsigned long long)d[w].q[b]);
+        }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const int tot = n * NB;
     for (int s = lane; s < tot; s += 64) {
@@ -600,23 +636,24 @@ __device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep
         const unsigned long long q = *(volatile unsigned long long*)&S->q[item][bin];
         if (q != 0) atomicAdd(A.J + (size_t)cell * (size_t)A.nbp + (size_t)bin, q);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
-template <int NB>
-__device__ __forceinline__ void deposit_wave(const TraceArgs& A, const Dep<NB>& d, DepScratch<NB>* S)
-{
-    if constexpr (ARC_DEDUP == 1)
-        deposit_wave_dedup<NB>(A, d, S);
-    else
-        deposit_wave_plain<NB>(A, d);
-}
-
-// Wave-wide deposit of the crossings of one pass: add() once per segment, by every lane.
+// Wave-wide deposit of the crossings of a pass: add() once per window of kDepWindow
+// segments, by every lane.
 template <int NB>
 struct Depositor {
     const TraceArgs& A;
     DepScratch<NB>* scratch;
-    __device__ void add(const Dep<NB>& d) { deposit_wave<NB>(A, d, scratch); }
+    __device__ void add(const Dep<NB> (&d)[kDepWindow])
+    {
+        if constexpr (ARC_DEDUP == 1) {
+            deposit_wave_dedup<NB>(A, d, scratch);
+        } else {
+#pragma unroll
+            for (int w = 0; w < kDepWindow; ++w) deposit_wave_plain<NB>(A, d[w]);
+        }
+    }
     __device__ void flush() {}
 };
 

@@ -380,7 +380,7 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 constexpr int kStackCap = 256;  // power of two, >= 3 * 64 children of one split round
 
 template <int NB, int PREC, int WPB>
-__global__ __launch_bounds__(WPB * 64) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
+__global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
                                                                const uint32_t* n_items_dev, uint32_t* head,
                                                                RayRec* __restrict__ spill_all, uint32_t spill_cap,
                                                                int refill)
