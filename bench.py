@@ -26,10 +26,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # and WRITE_SIZE (x1.0) on this workload, valid for the kernel sources with these digests; with
 # any other sources the figure is stale and the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "bytes_per_crossing": 41.15,
+    "bytes_per_crossing": 37.67,
     "sha256": {
-        "paper_1807_07094_amd/csrc/arc_device.h": "99b1d39b1d69a502ce7ea64564901aa232b1a618c02e16a2f2e933fb3a9f9e86",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "db14f6b6b2093fb5dd56551819a6a691cd6a1304f53975fe5d6c0832389d7e85",
+        "paper_1807_07094_amd/csrc/arc_device.h": "a685c225a36f213ea48834af1c36c3251e0ace44216741ccf259ea88dadd5719",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "42ad637e4ad50bd10bb8662078483cbfb9a1d9850c86a7ea6e2408886349fd79",
     },
     "profile": "profiles/hbm_traffic_grf1024_16384src.md",
 }

@@ -50,9 +50,8 @@ struct arc_ctx {
     uint32_t* u32 = nullptr;                  // [0] n_out, [1] queue head
     int* errflag = nullptr;
     unsigned long long* chem_stats = nullptr;
-    uint32_t* fallback = nullptr;             // learned step: cells for the plain solver
-    uint32_t* seg_counts = nullptr;           // learned step: per list segment, stride 16
-    size_t fallback_cap = 0;
+    unsigned long long* reject = nullptr;     // learned step: cells for the plain solver, a bit each
+    size_t reject_cap = 0;                    // words
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool timed_kernel = false;  // ev[4], ev[5] bracket the dominant trace kernel
     // last trace
@@ -253,7 +252,7 @@ void arc_destroy(arc_ctx* c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     void* bufs[] = {c->kappa, c->J, c->src, c->src_pos, c->src_ndot, c->src_order, c->dirs, c->rays[0], c->rays[1],
-                    c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats, c->fallback, c->seg_counts};
+                    c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats, c->reject};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < 6; ++i)
@@ -1006,25 +1005,18 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     a.eps = p->eps;
     a.t_floor = p->t_floor;
     a.stats = c->chem_stats;
-    a.list = nullptr;
-    a.counts = nullptr;
-    a.seg = a.nseg = 0;
+    a.mask = nullptr;
     HIP_TRY(c, launch_zero_u64(c->chem_stats, 4, st));
     HIP_TRY(c, hipEventRecord(c->ev[0], st));
-    uint64_t n_fb = 0;
-    std::vector<uint32_t> seg_counts;
     if (p->mode != ARC_CHEM_PLAIN) {
-        const uint32_t seg = list_seg_cap(a.ncell);
-        const size_t need = (size_t)seg * kListSegs;
-        if (need > c->fallback_cap) {
-            if (c->fallback) HIP_TRY(c, hipFree(c->fallback));
-            c->fallback = nullptr;
-            c->fallback_cap = 0;
-            HIP_TRY(c, hipMalloc((void**)&c->fallback, need * sizeof(uint32_t)));
-            c->fallback_cap = need;
+        const size_t words = ((size_t)a.ncell + 63) / 64;
+        if (words > c->reject_cap) {
+            if (c->reject) HIP_TRY(c, hipFree(c->reject));
+            c->reject = nullptr;
+            c->reject_cap = 0;
+            HIP_TRY(c, hipMalloc((void**)&c->reject, words * sizeof(unsigned long long)));
+            c->reject_cap = words;
         }
-        if (!c->seg_counts) HIP_TRY(c, hipMalloc((void**)&c->seg_counts, 16 * kListSegs * sizeof(uint32_t)));
-        HIP_TRY(c, launch_zero_u64((unsigned long long*)c->seg_counts, 8 * kListSegs, st));
         mlp::InferArgs ia{};
         ia.model = p->mlp->model;
         ia.ncell = a.ncell;
@@ -1041,22 +1033,14 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
         ia.gate_tol = (float)p->gate_tol;
         ia.gate_min_count = (uint32_t)std::max(0, p->gate_min_count);
         ia.t_floor = (float)p->t_floor;
-        ia.fallback = c->fallback;
-        ia.seg_counts = c->seg_counts;
-        ia.seg = seg;
+        ia.reject = c->reject;
         ia.collisional = p->rates == 1 ? p->collisional : 0;
         HIP_TRY(c, mlp::launch_infer(ia, st));
         HIP_TRY(c, hipEventRecord(c->ev[2], st));
         if (p->mode == ARC_CHEM_MLP_GATED) {
-            a.list = c->fallback;
-            a.counts = c->seg_counts;
-            a.seg = seg;
-            a.nseg = kListSegs;
+            a.mask = c->reject;
             HIP_TRY(c, launch_chem(a, st));
         }
-        seg_counts.resize(16 * kListSegs);
-        HIP_TRY(c, hipMemcpyAsync(seg_counts.data(), c->seg_counts, seg_counts.size() * sizeof(uint32_t),
-                                  hipMemcpyDeviceToHost, st));
     } else {
         HIP_TRY(c, launch_chem(a, st));
     }
@@ -1064,7 +1048,6 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     unsigned long long cs[4];
     HIP_TRY(c, hipMemcpyAsync(cs, c->chem_stats, sizeof cs, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
-    for (uint32_t j = 0; j < seg_counts.size() / 16; ++j) n_fb += seg_counts[16 * j];
     if (stats) {
         stats->cells = a.ncell;
         stats->sub_total = (int64_t)cs[0];
@@ -1073,7 +1056,7 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
         float ms = 0;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
         stats->ms = ms;
-        stats->fallback = p->mode == ARC_CHEM_MLP_GATED ? (int64_t)n_fb : 0;
+        stats->fallback = p->mode == ARC_CHEM_MLP_GATED ? (int64_t)cs[3] : 0;
         stats->ms_mlp = 0;
         if (p->mode != ARC_CHEM_PLAIN) {
             HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[2]));

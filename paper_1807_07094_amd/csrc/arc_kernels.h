@@ -45,18 +45,10 @@ struct ChemArgs {
     double dt;
     int isothermal, rates, collisional, max_sub;
     double alpha_hii, eps, t_floor;
-    unsigned long long* stats;  // [0] sub total, [1] capped, [2] max
-    // optional cell list in segments: segment j holds list[j * seg .. j * seg + counts[16 j])
-    const uint32_t* list;
-    const uint32_t* counts;
-    uint32_t seg, nseg;
+    unsigned long long* stats;  // [0] sub total, [1] capped, [2] max, [3] cells updated
+    // optional: update only the cells whose bit is set, bit (c mod 64) of word c / 64
+    const unsigned long long* mask;
 };
-
-// Fallback lists of the learned step: tile t (64 cells) appends to segment t mod kListSegs,
-// whose counter sits alone in a 64-byte line (counts[16 j]); a segment holds at most
-// ceil(tiles / kListSegs) * 64 cells.
-constexpr uint32_t kListSegs = 1024;
-inline uint32_t list_seg_cap(uint32_t ncell) { return ((ncell + 63) / 64 + kListSegs - 1) / kListSegs * 64; }
 
 hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);

@@ -619,14 +619,10 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a)
 {
     unsigned long long sub_total = 0, capped = 0;
     unsigned int sub_max = 0;
-    const size_t n_todo = a.list ? (size_t)a.seg * a.nseg : a.ncell;
-    for (size_t ii = blockIdx.x * (size_t)blockDim.x + threadIdx.x; ii < n_todo; ii += (size_t)gridDim.x * blockDim.x) {
-        uint32_t c = (uint32_t)ii;
-        if (a.list) {
-            const uint32_t j = (uint32_t)(ii / a.seg), off = (uint32_t)(ii - (size_t)j * a.seg);
-            if (off >= a.counts[16 * j]) continue;
-            c = a.list[ii];
-        }
+    unsigned long long cells = 0;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
+        if (a.mask && !((a.mask[c >> 6] >> (c & 63)) & 1ull)) continue;
+        ++cells;
         const double nh = a.n_h[c], nhe = a.y * nh;
         double nhi = nh * (double)a.x_hi[c], nhii = nh - nhi;
         double nhei = nhe * (double)a.x_hei[c], nheii = nhe * (double)a.x_heii[c];
@@ -707,17 +703,19 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a)
     }
     sub_total = wave_sum_u64(sub_total);
     capped = wave_sum_u64(capped);
+    cells = wave_sum_u64(cells);
     for (int off = 32; off > 0; off >>= 1) sub_max = max(sub_max, (unsigned)__shfl_xor((int)sub_max, off, 64));
     if ((threadIdx.x & 63) == 0) {
         if (sub_total) atomicAdd(&a.stats[0], sub_total);
         if (capped) atomicAdd(&a.stats[1], capped);
         atomicMax(&a.stats[2], (unsigned long long)sub_max);
+        if (cells) atomicAdd(&a.stats[3], cells);
     }
 }
 
 hipError_t launch_chem(const ChemArgs& a, hipStream_t s)
 {
-    k_chem<<<grid_for(a.list ? (size_t)a.seg * a.nseg : a.ncell, 256, 1u << 16), 256, 0, s>>>(a);
+    k_chem<<<grid_for(a.ncell, 256, 1u << 16), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -59,9 +59,7 @@ struct InferArgs {
     float gate_tol;
     uint32_t gate_min_count;
     float t_floor;
-    uint32_t* fallback;             // cells that failed the gate, in kListSegs segments of seg
-    uint32_t* seg_counts;           // per segment, stride 16 (one 64-byte line each)
-    uint32_t seg;
+    unsigned long long* reject;     // per 64-cell tile, bit set = the plain solver updates the cell
     int collisional;
 };
 

@@ -20,7 +20,6 @@
 #include <math.h>
 
 #include "arc_chem.h"
-#include "arc_kernels.h"
 #include "arc_mlp.h"
 
 namespace arc {
@@ -151,73 +150,82 @@ __device__ __forceinline__ void load_model(const Model* m, SharedModel& s)
 // receives rows 4q..4q+3 of column n, which are exactly 4 of the 8 depth values that lane must
 // supply as the B operand of the next layer, provided that layer's depth slots are taken in
 // the order perm_k: slot 8q + i of k-step s stands for input unit 32s + 4q + i (i < 4) or
-// 32s + 16 + 4q + i - 4 (i >= 4). The A operands (weights) are loaded in that same order,
-// so no activation leaves the registers.
+// 32s + 16 + 4q + i - 4 (i >= 4). The A operands (weights) are laid out in LDS in that same
+// order, so no activation leaves the registers.
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ int perm_k(int s, int q, int i) { return 32 * s + (i < 4 ? 4 * q + i : 12 + 4 * q + i); }
 
-struct LaneWeights {
-    bf16x8 a1[4];       // layer 1, M-tile t: W1[16t + m][8q + i]
-    bf16x8 a2[4][2];    // layer 2, M-tile t, k-step s: W2[16t + m][perm_k(s, q, i)]
-    bf16x8 a3[2];       // layer 3, k-step s: W3[m][perm_k(s, q, i)] (rows >= kOut are zero)
-    float b1[4][4];     // biases of the rows this lane receives: b[16t + 4q + r]
-    float b2[4][4];
+// The weights as the operand fragments each lane supplies, in LDS (shared by the block):
+// frag[f][lane] for f = 0..3 layer 1 (M-tile t = f), 4..11 layer 2 (t = (f - 4) / 2,
+// k-step s = (f - 4) % 2), 12..13 layer 3 (k-step s = f - 12); biases as float4 per four rows.
+constexpr int kFrags = 14;
+struct LdsWeights {
+    bf16x8 frag[kFrags][64];
+    float4 b1[kHid / 4], b2[kHid / 4];
     float b3[kOut];
 };
 
-__device__ __forceinline__ void load_lane_weights(const Model* M, LaneWeights& w)
+// Called by the whole block, followed by a barrier.
+__device__ __forceinline__ void load_lds_weights(const Model* M, LdsWeights& L)
 {
-    const int lane = threadIdx.x & 63, m = lane & 15, q = lane >> 4;
+    for (int idx = threadIdx.x; idx < kFrags * 64; idx += blockDim.x) {
+        const int f = idx >> 6, l = idx & 63, m = l & 15, q = l >> 4;
+        bf16x8 v;
+        if (f < 4) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+            for (int i = 0; i < 8; ++i) v[i] = M->w1t[16 * f + m][8 * q + i];
+        } else if (f < 12) {
+            const int t = (f - 4) >> 1, s2 = (f - 4) & 1;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) w.a1[t][i] = M->w1t[16 * t + m][8 * q + i];
+            for (int i = 0; i < 8; ++i) v[i] = M->w2t[16 * t + m][perm_k(s2, q, i)];
+        } else {
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) w.a2[t][s2][i] = M->w2t[16 * t + m][perm_k(s2, q, i)];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            w.b1[t][r] = M->b1[16 * t + 4 * q + r];
-            w.b2[t][r] = M->b2[16 * t + 4 * q + r];
+            for (int i = 0; i < 8; ++i) v[i] = M->w3t[m][perm_k(f - 12, q, i)];
         }
+        L.frag[f][l] = v;
     }
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) w.a3[s2][i] = M->w3t[m][perm_k(s2, q, i)];
-#pragma unroll
-    for (int k = 0; k < kOut; ++k) w.b3[k] = M->b3[k];
+    for (int i = threadIdx.x; i < kHid / 4; i += blockDim.x) {
+        L.b1[i] = make_float4(M->b1[4 * i], M->b1[4 * i + 1], M->b1[4 * i + 2], M->b1[4 * i + 3]);
+        L.b2[i] = make_float4(M->b2[4 * i], M->b2[4 * i + 1], M->b2[4 * i + 2], M->b2[4 * i + 3]);
+    }
+    if (threadIdx.x < kOut) L.b3[threadIdx.x] = M->b3[threadIdx.x];
 }
 
 // Hidden layer: bias, ReLU and BF16 rounding of four M-tiles, packed as the two k-steps of
 // the next layer's B operand.
-__device__ __forceinline__ void hidden_to_operand(const f32x4 d[4], const float b[4][4], bf16x8 h[2])
+__device__ __forceinline__ void hidden_to_operand(const f32x4 d[4], const float4* bias, bf16x8 h[2])
 {
+    const int q = (threadIdx.x & 63) >> 4;
 #pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            h[s2][r] = (__bf16)act(d[2 * s2][r] + b[2 * s2][r]);
-            h[s2][4 + r] = (__bf16)act(d[2 * s2 + 1][r] + b[2 * s2 + 1][r]);
-        }
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const float4 b0 = bias[4 * (2 * s2) + q], b1 = bias[4 * (2 * s2 + 1) + q];
+        h[s2][0] = (__bf16)act(d[2 * s2][0] + b0.x);
+        h[s2][1] = (__bf16)act(d[2 * s2][1] + b0.y);
+        h[s2][2] = (__bf16)act(d[2 * s2][2] + b0.z);
+        h[s2][3] = (__bf16)act(d[2 * s2][3] + b0.w);
+        h[s2][4] = (__bf16)act(d[2 * s2 + 1][0] + b1.x);
+        h[s2][5] = (__bf16)act(d[2 * s2 + 1][1] + b1.y);
+        h[s2][6] = (__bf16)act(d[2 * s2 + 1][2] + b1.z);
+        h[s2][7] = (__bf16)act(d[2 * s2 + 1][3] + b1.w);
+    }
 }
 
 // One tile of 16 cells: x = the layer-1 B operand (lanes with q = 0 hold the 8 standardised
 // features of cell n, other lanes zeros). Returns rows 4q..4q+3 of the output tile; lanes
 // with q = 0 hold the two outputs of cell n in elements 0 and 1 (biases included).
-__device__ __forceinline__ f32x4 forward_tile(const LaneWeights& w, bf16x8 x)
+__device__ __forceinline__ f32x4 forward_tile(const LdsWeights& w, bf16x8 x)
 {
+    const int lane = threadIdx.x & 63;
     const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 d[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) d[t] = mfma(w.a1[t], x, z);
+    for (int t = 0; t < 4; ++t) d[t] = mfma(w.frag[t][lane], x, z);
     bf16x8 h[2];
     hidden_to_operand(d, w.b1, h);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) d[t] = mfma(w.a2[t][1], h[1], mfma(w.a2[t][0], h[0], z));
+    for (int t = 0; t < 4; ++t) d[t] = mfma(w.frag[5 + 2 * t][lane], h[1], mfma(w.frag[4 + 2 * t][lane], h[0], z));
     hidden_to_operand(d, w.b2, h);
-    f32x4 o = mfma(w.a3[1], h[1], mfma(w.a3[0], h[0], z));
+    f32x4 o = mfma(w.frag[13][lane], h[1], mfma(w.frag[12][lane], h[0], z));
     o[0] += w.b3[0];
     o[1] += w.b3[1];
     return o;
@@ -225,7 +233,7 @@ __device__ __forceinline__ f32x4 forward_tile(const LaneWeights& w, bf16x8 x)
 
 // Forward pass of the 64 cells of a wave, one per lane: f = the lane's standardised
 // features; returns the lane's two outputs.
-__device__ __forceinline__ void forward_wave(const LaneWeights& w, const float f[kIn], float& o0, float& o1)
+__device__ __forceinline__ void forward_wave(const LdsWeights& w, const float f[kIn], float& o0, float& o1)
 {
     const int lane = threadIdx.x & 63, n = lane & 15, q = lane >> 4;
     // the eight features as four packed BF16 pairs
@@ -301,10 +309,10 @@ __device__ __forceinline__ void standardise(const Model* M, bool valid, float f[
 __global__ __launch_bounds__(256) void k_infer(InferArgs a)
 {
     const Model* M = a.model;
-    LaneWeights w;
-    load_lane_weights(M, w);
+    __shared__ LdsWeights w;
+    load_lds_weights(M, w);
+    __syncthreads();
     const int lane = threadIdx.x & 63;
-    const uint64_t lt = __lanemask_lt();
     const float dtf = (float)a.dt, ldt = log10f(dtf);
     const float yf = (float)a.y;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -323,52 +331,50 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
         }
         float f[kIn];
         cell_features(nh, x0, T, gam, ldt, h, xheii, xhei, f);
-        float raw[kGateDims];
+        // (1) gate bins: inside the training range, in a bin with enough samples and a small
+        //     held-out error
+        bool accept = valid;
+        if (valid && a.gated) {
+            uint32_t bin = 0;
 #pragma unroll
-        for (int k = 0; k < kGateDims; ++k) raw[k] = f[k];
-        standardise(M, valid, f);
-        float o0, o1;
-        forward_wave(w, f, o0, o1);
-        bool accept = false;
-        float xn = 0.0f, Tn = 0.0f;
-        if (valid) {
-            accept = true;
-            if (a.gated) {
-                // (1) inside the training range, in a bin with enough samples and a small
-                //     held-out error
-                uint32_t bin = 0;
-#pragma unroll
-                for (int k = kGateDims - 1; k >= 0; --k) {
-                    const float u = (raw[k] - M->lo[k]) / (M->hi[k] - M->lo[k]);
-                    accept = accept && u >= 0.0f && u <= 1.0f;
-                    const int b = min(kGate - 1, max(0, (int)(u * kGate)));
-                    bin = bin * kGate + (uint32_t)b;
-                }
-                accept = accept && M->gate_count[bin] >= a.gate_min_count && M->gate_err[bin] <= a.gate_tol;
+            for (int k = kGateDims - 1; k >= 0; --k) {
+                const float u = (f[k] - M->lo[k]) / (M->hi[k] - M->lo[k]);
+                accept = accept && u >= 0.0f && u <= 1.0f;
+                const int b = min(kGate - 1, max(0, (int)(u * kGate)));
+                bin = bin * kGate + (uint32_t)b;
             }
+            accept = accept && M->gate_count[bin] >= a.gate_min_count && M->gate_err[bin] <= a.gate_tol;
+        }
+        float xn = 0.0f, Tn = 0.0f;
+        // the network runs only for waves with a cell past the gate bins (wave-uniform branch)
+        if (__ballot(accept)) {
+            standardise(M, valid, f);
+            float o0, o1;
+            forward_wave(w, f, o0, o1);
             // the outputs (the baseline only where they can still be used)
             if (accept) {
                 xb = x_baseline(nh, x0, T, gam, xheii, xhei, dtf, M->base_y, M->base_collisional);
                 xn = fminf(fmaxf(xb + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
                 Tn = T * exp10f(o1 * M->out_sd[1] + M->out_mu[1]);
             }
+        }
+        if (accept) {
             if (a.gated) {
                 // (2) physical output temperature
                 accept = accept && Tn >= a.t_floor && Tn < 1e9f;
                 // (3) helium close to steady over dt (the network does not predict helium)
+                //     (a screening test: FP32 is ample for a 1e-3 threshold)
                 if (accept && a.y > 0.0) {
-                    const double nhd = nh, nhe = a.y * nhd;
-                    const double nhei = nhe * xhei, nheii = nhe * xheii;
-                    const double nheiii = fmax(0.0, nhe - nhei - nheii);
-                    const double nhii = nhd * (1.0 - x0);
-                    const double ne = nhii + nheii + 2.0 * nheiii;
+                    const float nhe = yf * nh;
+                    const float nhei = nhe * xhei, nheii = nhe * xheii;
+                    const float nheiii = fmaxf(0.0f, nhe - nhei - nheii);
+                    const float ne = nh * (1.0f - x0) + nheii + 2.0f * nheiii;
                     const chem::Coef k = chem::coefficients(T);
-                    const double kc = a.collisional ? 1.0 : 0.0;
-                    const double dhei = (double)k.a_heii * ne * nheii -
-                                        ((double)a.gamma[(size_t)a.ncell + c] + kc * k.k_hei * ne) * nhei;
-                    const double dheiii = ((double)a.gamma[2 * (size_t)a.ncell + c] + kc * k.k_heii * ne) * nheii -
-                                          (double)k.a_heiii * ne * nheiii;
-                    accept = fabs(dhei) * a.dt <= 1e-3 * nhe && fabs(dheiii) * a.dt <= 1e-3 * nhe;
+                    const float kc = a.collisional ? 1.0f : 0.0f;
+                    const float dhei = k.a_heii * ne * nheii - (a.gamma[(size_t)a.ncell + c] + kc * k.k_hei * ne) * nhei;
+                    const float dheiii =
+                        (a.gamma[2 * (size_t)a.ncell + c] + kc * k.k_heii * ne) * nheii - k.a_heiii * ne * nheiii;
+                    accept = fabsf(dhei) * dtf <= 1e-3f * nhe && fabsf(dheiii) * dtf <= 1e-3f * nhe;
                 }
             }
         }
@@ -376,17 +382,9 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
             a.x_hi[c] = xn;
             a.temp[c] = Tn;
         }
-        // rejected cells join the list segment of this tile (one atomic per wave, on a
-        // counter shared by 1 / kListSegs of the tiles)
+        // the cells for the plain solver, one bit per cell of the tile
         const uint64_t rej = __ballot(valid && !accept);
-        if (rej) {
-            const int leader = __ffsll((unsigned long long)rej) - 1;
-            const uint32_t j = (base >> 6) & (kListSegs - 1);
-            uint32_t w0 = 0;
-            if (lane == leader) w0 = atomicAdd(a.seg_counts + 16 * j, (uint32_t)__popcll(rej));
-            w0 = __shfl(w0, leader, 64);
-            if (valid && !accept) a.fallback[(size_t)j * a.seg + w0 + (uint32_t)__popcll(rej & lt)] = c;
-        }
+        if (lane == 0) a.reject[base >> 6] = (unsigned long long)rej;
     }
 }
 
@@ -415,8 +413,9 @@ __device__ __forceinline__ float raw_baseline(const float* x, float y, int colli
 __global__ __launch_bounds__(256) void k_predict(const Model* M, const float* X, const uint32_t* idx, uint32_t m,
                                                  float* P)
 {
-    LaneWeights w;
-    load_lane_weights(M, w);
+    __shared__ LdsWeights w;
+    load_lds_weights(M, w);
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + lane;
