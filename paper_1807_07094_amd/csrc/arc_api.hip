@@ -49,7 +49,7 @@ struct arc_ctx {
     double* acc = nullptr;                    // [0..3] escaped per bin, [4] absorbed
     uint32_t* u32 = nullptr;                  // [0] n_out, [1] queue head
     int* errflag = nullptr;
-    unsigned long long* chem_stats = nullptr;
+    unsigned long long* chem_stats = nullptr;  // [0..3] chemistry statistics, [4] work counter
     unsigned long long* reject = nullptr;     // learned step: cells for the plain solver, a bit each
     size_t reject_cap = 0;                    // words
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -236,7 +236,7 @@ arc_status arc_create(int32_t device, arc_ctx** out)
               hipMalloc((void**)&c->acc, 8 * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&c->u32, 4 * sizeof(uint32_t)) == hipSuccess &&
               hipMalloc((void**)&c->errflag, sizeof(int)) == hipSuccess &&
-              hipMalloc((void**)&c->chem_stats, 4 * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc((void**)&c->chem_stats, 5 * sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc((void**)&c->sums, 2 * sizeof(unsigned long long)) == hipSuccess;
     for (int i = 0; i < 6 && ok; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
     if (!ok) {
@@ -1006,7 +1006,8 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     a.t_floor = p->t_floor;
     a.stats = c->chem_stats;
     a.mask = nullptr;
-    HIP_TRY(c, launch_zero_u64(c->chem_stats, 4, st));
+    HIP_TRY(c, launch_zero_u64(c->chem_stats, 5, st));
+    a.chunk_counter = (uint32_t*)(c->chem_stats + 4);
     HIP_TRY(c, hipEventRecord(c->ev[0], st));
     if (p->mode != ARC_CHEM_PLAIN) {
         const size_t words = ((size_t)a.ncell + 63) / 64;

@@ -46,6 +46,7 @@ struct ChemArgs {
     int isothermal, rates, collisional, max_sub;
     double alpha_hii, eps, t_floor;
     unsigned long long* stats;  // [0] sub total, [1] capped, [2] max, [3] cells updated
+    uint32_t* chunk_counter;    // zero before the launch
     // optional: update only the cells whose bit is set, bit (c mod 64) of word c / 64
     const unsigned long long* mask;
 };
