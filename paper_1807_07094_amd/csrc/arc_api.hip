@@ -433,8 +433,10 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     fa.nbp = nbp;
     fa.nx = g->nx;
     fa.ny = g->ny;
+    fa.nz = g->nz;
     fa.nbx8 = nbx8;
     fa.nby8 = nby8;
+    fa.nbz8 = nbz8;
     fa.ncell = (uint32_t)ncell;
     const double L2 = g->cell_cm * g->cell_cm;
     for (int k = 0; k < nb; ++k) {

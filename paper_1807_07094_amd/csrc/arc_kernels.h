@@ -24,7 +24,7 @@ struct OpacityArgs {
 
 struct FinalizeArgs {
     int nb, nbp;
-    int nx, ny, nbx8, nby8;
+    int nx, ny, nz, nbx8, nby8, nbz8;
     uint32_t ncell;
     double gam[kMaxBins][3];   // u_J,b sigma_bS / L^2
     double hea[kMaxBins][3];   // u_J,b sigma_bS (E_b - E_S)^+ / L^2

@@ -98,44 +98,82 @@ __device__ __forceinline__ uint32_t gather3(uint32_t m)
     return (m & 1u) | ((m >> 2) & 2u) | ((m >> 4) & 4u);
 }
 
+// The grid is handled in regions of 32 x 8 x 8 cells: four consecutive 8^3 blocks of the
+// blocked layout, and 64 x-rows of 32 cells (whole 128-byte lines) of the linear arrays. One
+// workgroup per region transposes between the two orders through LDS, so that both sides
+// are read and written in whole lines.
+constexpr int kRegionCells = 2048;
+
+struct Region {
+    uint32_t x0, y0, z0;  // first cell
+    uint32_t base;        // blocked index of its first cell
+    uint32_t cells;       // cells of the blocked layout it covers (512 per block)
+};
+
+__device__ __forceinline__ Region region_of(uint32_t r, int nbx8, int nby8)
+{
+    const uint32_t nrx = ((uint32_t)nbx8 + 3u) / 4u;
+    const uint32_t rx = r % nrx, by = (r / nrx) % (uint32_t)nby8, bz = r / (nrx * (uint32_t)nby8);
+    Region g;
+    g.x0 = rx * 32u;
+    g.y0 = by * 8u;
+    g.z0 = bz * 8u;
+    g.base = ((bz * (uint32_t)nby8 + by) * (uint32_t)nbx8 + 4u * rx) << 9;
+    g.cells = min(4u, (uint32_t)nbx8 - 4u * rx) << 9;
+    return g;
+}
+
+// Position l in [0, 2048) of the region's linear order (x fastest) <-> its offset in the
+// region's blocked range.
+__device__ __forceinline__ uint32_t region_blocked_offset(uint32_t l)
+{
+    const uint32_t xl = l & 31u, yl = (l >> 5) & 7u, zl = l >> 8;
+    return ((xl >> 3) << 9) | spread3(xl & 7u) | (spread3(yl) << 1) | (spread3(zl) << 2);
+}
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_opacity(OpacityArgs a)
 {
-    // one thread per cell of the blocked layout: contiguous writes, gathered reads
-    const uint32_t nblk = (uint32_t)a.nbx8 * (uint32_t)a.nby8 * (uint32_t)a.nbz8;
-    const uint32_t total = nblk << 9;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        const uint32_t b = i >> 9, m = i & 511u;
-        const int x = (int)((b % (uint32_t)a.nbx8) * 8u + gather3(m));
-        const int y = (int)(((b / (uint32_t)a.nbx8) % (uint32_t)a.nby8) * 8u + gather3(m >> 1));
-        const int z = (int)((b / ((uint32_t)a.nbx8 * (uint32_t)a.nby8)) * 8u + gather3(m >> 2));
-        if (x >= a.nx || y >= a.ny || z >= a.nz) continue;
-        const uint32_t c = (uint32_t)x + (uint32_t)a.nx * ((uint32_t)y + (uint32_t)a.ny * (uint32_t)z);
-        const float n = a.n_h[c], xh = a.x_hi[c], x1 = a.x_hei[c], x2 = a.x_heii[c];
-        const bool ok = isfinite(n) && n > 0.0f && xh >= 0.0f && xh <= 1.0f && x1 >= 0.0f && x1 <= 1.0f &&
-                        x2 >= 0.0f && x2 <= 1.0f;
-        if (!ok) atomicOr(a.errflag, 1);
-        float k[kMaxBins] = {0.0f, 0.0f, 0.0f, 0.0f};
+    __shared__ float4 st[kRegionCells];
+    const uint32_t nreg = (((uint32_t)a.nbx8 + 3u) / 4u) * (uint32_t)a.nby8 * (uint32_t)a.nbz8;
+    for (uint32_t r = blockIdx.x; r < nreg; r += gridDim.x) {
+        const Region g = region_of(r, a.nbx8, a.nby8);
+        // linear reads along x-rows, opacities into LDS at their blocked offsets
+        for (uint32_t l = threadIdx.x; l < (uint32_t)kRegionCells; l += blockDim.x) {
+            const uint32_t x = g.x0 + (l & 31u), y = g.y0 + ((l >> 5) & 7u), z = g.z0 + (l >> 8);
+            float k[kMaxBins] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (x < (uint32_t)a.nx && y < (uint32_t)a.ny && z < (uint32_t)a.nz) {
+                const uint32_t c = x + (uint32_t)a.nx * (y + (uint32_t)a.ny * z);
+                const float n = a.n_h[c], xh = a.x_hi[c], x1 = a.x_hei[c], x2 = a.x_heii[c];
+                const bool ok = isfinite(n) && n > 0.0f && xh >= 0.0f && xh <= 1.0f && x1 >= 0.0f && x1 <= 1.0f &&
+                                x2 >= 0.0f && x2 <= 1.0f;
+                if (!ok) atomicOr(a.errflag, 1);
 #pragma unroll
-        for (int bb = 0; bb < NB; ++bb)
-            k[bb] = (float)(a.L * (double)n *
-                            (a.sigma[bb][0] * (double)xh + a.y * (a.sigma[bb][1] * (double)x1 + a.sigma[bb][2] * (double)x2)));
-        if constexpr (NB == 1) {
-            a.kappa1[i] = k[0];
-            a.J[i] = 0ull;
-        } else {
-            a.kappa4[i] = make_float4(k[0], k[1], k[2], k[3]);
-            unsigned long long* j = a.J + (size_t)i * a.nbp;
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb)
-                if (bb < a.nbp) j[bb] = 0ull;
+                for (int bb = 0; bb < NB; ++bb)
+                    k[bb] = (float)(a.L * (double)n *
+                                    (a.sigma[bb][0] * (double)xh +
+                                     a.y * (a.sigma[bb][1] * (double)x1 + a.sigma[bb][2] * (double)x2)));
+            }
+            const uint32_t o = region_blocked_offset(l);
+            if (o < g.cells) st[o] = make_float4(k[0], k[1], k[2], k[3]);
         }
+        __syncthreads();
+        // contiguous writes of the blocked range: opacity, and the zeroed field
+        for (uint32_t o = threadIdx.x; o < g.cells; o += blockDim.x) {
+            if constexpr (NB == 1)
+                a.kappa1[g.base + o] = st[o].x;
+            else
+                a.kappa4[g.base + o] = st[o];
+        }
+        const uint32_t words = g.cells * (uint32_t)a.nbp;
+        for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) a.J[(size_t)g.base * a.nbp + w] = 0ull;
+        __syncthreads();
     }
 }
 
 hipError_t launch_opacity(const OpacityArgs& a, hipStream_t s)
 {
-    const unsigned g = grid_for((size_t)a.nbx8 * a.nby8 * a.nbz8 * 512, 256, 1u << 20);
+    const unsigned g = grid_for((size_t)((a.nbx8 + 3) / 4) * a.nby8 * a.nbz8, 1, 1u << 16);
     switch (a.nb) {
         case 1: k_opacity<1><<<g, 256, 0, s>>>(a); break;
         case 2: k_opacity<2><<<g, 256, 0, s>>>(a); break;
@@ -541,38 +579,58 @@ hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* i
 template <int NB>
 __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a)
 {
+    // per region: contiguous reads of the field and opacity, rates into LDS in linear
+    // order, then whole x-rows of the six rate arrays
+    __shared__ float out[6][kRegionCells];
     double absorbed = 0.0;
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
-        const uint32_t x = c % (uint32_t)a.nx, y = (c / (uint32_t)a.nx) % (uint32_t)a.ny,
-                       z = c / ((uint32_t)a.nx * (uint32_t)a.ny);
-        const uint32_t i = blocked_index((int)x, (int)y, (int)z, a.nbx8, a.nby8);
-        double Jb[NB];
-        const unsigned long long* j = a.J + (size_t)i * a.nbp;
+    const uint32_t nreg = (((uint32_t)a.nbx8 + 3u) / 4u) * (uint32_t)a.nby8 * (uint32_t)a.nbz8;
+    for (uint32_t r = blockIdx.x; r < nreg; r += gridDim.x) {
+        const Region g = region_of(r, a.nbx8, a.nby8);
+        for (uint32_t o = threadIdx.x; o < g.cells; o += blockDim.x) {
+            const uint32_t i = g.base + o, m = o & 511u;
+            const uint32_t xl = ((o >> 9) << 3) | gather3(m), yl = gather3(m >> 1), zl = gather3(m >> 2);
+            const uint32_t l = (zl << 8) | (yl << 5) | xl;
+            double Jb[NB];
+            const unsigned long long* j = a.J + (size_t)i * a.nbp;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) Jb[b] = (double)(long long)j[b];
-        float k[NB];
-        if constexpr (NB == 1) {
-            k[0] = a.kappa1[i];
-        } else {
-            const float4 v = a.kappa4[i];
-            k[0] = v.x;
-            k[1] = v.y;
-            if constexpr (NB > 2) k[2] = v.z;
-            if constexpr (NB > 3) k[3] = v.w;
-        }
-#pragma unroll
-        for (int sp = 0; sp < 3; ++sp) {
-            double g = 0.0, h = 0.0;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                g += a.gam[b][sp] * Jb[b];
-                h += a.hea[b][sp] * Jb[b];
+            for (int b = 0; b < NB; ++b) Jb[b] = (double)(long long)j[b];
+            float k[NB];
+            if constexpr (NB == 1) {
+                k[0] = a.kappa1[i];
+            } else {
+                const float4 v = a.kappa4[i];
+                k[0] = v.x;
+                k[1] = v.y;
+                if constexpr (NB > 2) k[2] = v.z;
+                if constexpr (NB > 3) k[3] = v.w;
             }
-            a.gamma[(size_t)sp * a.ncell + c] = (float)g;
-            a.heat[(size_t)sp * a.ncell + c] = (float)h;
-        }
 #pragma unroll
-        for (int b = 0; b < NB; ++b) absorbed += a.uj[b] * Jb[b] * (double)k[b];
+            for (int sp = 0; sp < 3; ++sp) {
+                double gm = 0.0, h = 0.0;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    gm += a.gam[b][sp] * Jb[b];
+                    h += a.hea[b][sp] * Jb[b];
+                }
+                out[sp][l] = (float)gm;
+                out[3 + sp][l] = (float)h;
+            }
+            // cells of padding blocks have a zero field
+#pragma unroll
+            for (int b = 0; b < NB; ++b) absorbed += a.uj[b] * Jb[b] * (double)k[b];
+        }
+        __syncthreads();
+        for (uint32_t l = threadIdx.x; l < (uint32_t)kRegionCells; l += blockDim.x) {
+            const uint32_t x = g.x0 + (l & 31u), y = g.y0 + ((l >> 5) & 7u), z = g.z0 + (l >> 8);
+            if (x >= (uint32_t)a.nx || y >= (uint32_t)a.ny || z >= (uint32_t)a.nz) continue;
+            const size_t c = x + (size_t)a.nx * (y + (size_t)a.ny * z);
+#pragma unroll
+            for (int sp = 0; sp < 3; ++sp) {
+                a.gamma[(size_t)sp * a.ncell + c] = out[sp][l];
+                a.heat[(size_t)sp * a.ncell + c] = out[3 + sp][l];
+            }
+        }
+        __syncthreads();
     }
     absorbed = wave_sum_f64(absorbed);
     if ((threadIdx.x & 63) == 0 && absorbed != 0.0) atomicAdd(a.absorbed, absorbed);
@@ -580,7 +638,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a)
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s)
 {
-    const unsigned g = grid_for(a.ncell, 256, 1u << 16);
+    const unsigned g = grid_for((size_t)((a.nbx8 + 3) / 4) * a.nby8 * a.nbz8, 1, 1u << 16);
     switch (a.nb) {
         case 1: k_finalize<1><<<g, 256, 0, s>>>(a); break;
         case 2: k_finalize<2><<<g, 256, 0, s>>>(a); break;
