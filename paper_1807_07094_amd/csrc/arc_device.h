@@ -20,6 +20,8 @@ constexpr float kDtauTermMin = 0.01f;  // a terminating crossing must be this th
 enum Event : int { kContinue = 0, kSplit = 1, kTerminate = 2, kEscape = 3 };
 
 constexpr uint32_t kNoCell = 0xFFFFFFFFu;
+// Pointer qualifier of the LDS address space.
+#define kLds __attribute__((address_space(3)))
 
 // Cell layout of the opacity and the field: 8^3 blocks in x-fastest block order, Morton
 // order inside a block, so that the 2x2x2 neighbourhood of a cell shares a 128-byte
@@ -575,10 +577,14 @@ __device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep
                                                    DepScratch<NB>* S)
 {
     constexpr int W = kDepWindow;
-    volatile uint32_t* slot_cell = S->slot_cell;
-    volatile uint8_t* slot_id = S->slot_id;
-    volatile uint8_t* slot_rank = S->slot_rank;
-    volatile uint32_t* st_cell = S->cell;
+    // LDS-qualified views: through a generic pointer the accesses would be FLAT instructions,
+    // which also wait for the wave's outstanding gathers and atomics
+    volatile kLds uint32_t* slot_cell = (volatile kLds uint32_t*)S->slot_cell;
+    volatile kLds uint8_t* slot_id = (volatile kLds uint8_t*)S->slot_id;
+    volatile kLds uint8_t* slot_rank = (volatile kLds uint8_t*)S->slot_rank;
+    volatile kLds uint32_t* st_cell = (volatile kLds uint32_t*)S->cell;
+    volatile kLds unsigned long long* st_q = (volatile kLds unsigned long long*)&S->q[0][0];
+    kLds unsigned long long* acc_q = (kLds unsigned long long*)&S->q[0][0];
     const int lane = threadIdx.x & 63;
     const uint64_t lt = __lanemask_lt();
     bool v[W], in[W], lead[W];
@@ -616,8 +622,7 @@ __device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep
         if (rank[w] >= 0) {
             st_cell[rank[w]] = d[w].cell;
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                *(volatile unsigned long long*)&S->q[rank[w]][b] = (unsigned long long)d[w].q[b];
+            for (int b = 0; b < NB; ++b) st_q[rank[w] * NB + b] = (unsigned long long)d[w].q[b];
         }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
@@ -626,14 +631,15 @@ __device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep
             const uint32_t r = slot_rank[h[w]];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
-                if (d[w].q[b] != 0) atomicAdd(&S->q[r][b], (unsigned long long)d[w].q[b]);
+                if (d[w].q[b] != 0) __hip_atomic_fetch_add(acc_q + r * NB + b, (unsigned long long)d[w].q[b],
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const int tot = n * NB;
     for (int s = lane; s < tot; s += 64) {
         const int item = s / NB, bin = s - item * NB;
         const uint32_t cell = st_cell[item];
-        const unsigned long long q = *(volatile unsigned long long*)&S->q[item][bin];
+        const unsigned long long q = st_q[item * NB + bin];
         if (q != 0) atomicAdd(A.J + (size_t)cell * (size_t)A.nbp + (size_t)bin, q);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");

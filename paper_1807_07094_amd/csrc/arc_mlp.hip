@@ -232,8 +232,10 @@ __device__ __forceinline__ f32x4 forward_tile(const LdsWeights& w, bf16x8 x)
 }
 
 // Forward pass of the 64 cells of a wave, one per lane: f = the lane's standardised
-// features; returns the lane's two outputs.
-__device__ __forceinline__ void forward_wave(const LdsWeights& w, const float f[kIn], float& o0, float& o1)
+// features; returns the lane's two outputs. Tiles of 16 cells with no bit in `need`
+// (wave-uniform) are skipped and their outputs left at zero.
+__device__ __forceinline__ void forward_wave(const LdsWeights& w, const float f[kIn], float& o0, float& o1,
+                                             uint64_t need = ~0ull)
 {
     const int lane = threadIdx.x & 63, n = lane & 15, q = lane >> 4;
     // the eight features as four packed BF16 pairs
@@ -247,6 +249,7 @@ __device__ __forceinline__ void forward_wave(const LdsWeights& w, const float f[
     o0 = o1 = 0.0f;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
+        if (((need >> (16 * c)) & 0xFFFFull) == 0) continue;  // no lane of these 16 cells needs it
         bf16x8 x;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -347,10 +350,11 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
         }
         float xn = 0.0f, Tn = 0.0f;
         // the network runs only for waves with a cell past the gate bins (wave-uniform branch)
-        if (__ballot(accept)) {
+        const uint64_t cand = __ballot(accept);
+        if (cand) {
             standardise(M, valid, f);
             float o0, o1;
-            forward_wave(w, f, o0, o1);
+            forward_wave(w, f, o0, o1, cand);
             // the outputs (the baseline only where they can still be used)
             if (accept) {
                 xb = x_baseline(nh, x0, T, gam, xheii, xhei, dtf, M->base_y, M->base_collisional);
