@@ -21,7 +21,7 @@ constexpr int kGate = 8;     // gate bins per input feature
 constexpr int kGateBins = kGate * kGate * kGate * kGate * kGate;
 static_assert(kGateDims == 5, "kGateBins spans five features");
 constexpr float kGammaFloor = 1e-30f;
-constexpr float kHeatFloor = 1e-40f;
+constexpr float kHeatFloor = 1e-35f;  // a normal float: the hardware log flushes denormals
 
 // Offsets of the FP32 master parameters in one flat array.
 constexpr int kW1 = 0;                      // [kIn][kHid]

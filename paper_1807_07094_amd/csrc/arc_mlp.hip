@@ -266,16 +266,20 @@ __device__ __forceinline__ void forward_wave(const LdsWeights& w, const float f[
     }
 }
 
-__device__ __forceinline__ float safe_log10(float v, float floor_) { return log10f(fmaxf(v, floor_)); }
+// Decimal logarithm and power from the hardware base-2 functions (the features and the
+// targets of training go through the same two functions as inference).
+__device__ __forceinline__ float flog10(float v) { return __builtin_amdgcn_logf(v) * 0.30102999566398120f; }
+__device__ __forceinline__ float fexp10(float v) { return __builtin_amdgcn_exp2f(v * 3.3219280948873623f); }
+__device__ __forceinline__ float safe_log10(float v, float floor_) { return flog10(fmaxf(v, floor_)); }
 
 // Features of a cell: n_H, x_HI, T, Gamma_HI, dt [s], h = photoheating per H atom, x_HeII, x_HeI.
 __device__ __forceinline__ void cell_features(float nh, float x, float T, float gam, float ldt, float h, float xheii,
                                               float xhei, float f[kIn])
 {
     static_assert(kIn == 8, "eight features fill the first MFMA depth group");
-    f[0] = log10f(nh);
+    f[0] = flog10(nh);
     f[1] = x;
-    f[2] = log10f(T);
+    f[2] = flog10(T);
     f[3] = safe_log10(gam, kGammaFloor);
     f[4] = ldt;
     f[5] = safe_log10(h, kHeatFloor);
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
     load_lds_weights(M, w);
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const float dtf = (float)a.dt, ldt = log10f(dtf);
+    const float dtf = (float)a.dt, ldt = flog10(dtf);
     const float yf = (float)a.y;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < a.ncell; base += stride) {
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
             if (accept) {
                 xb = x_baseline(nh, x0, T, gam, xheii, xhei, dtf, M->base_y, M->base_collisional);
                 xn = fminf(fmaxf(xb + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
-                Tn = T * exp10f(o1 * M->out_sd[1] + M->out_mu[1]);
+                Tn = T * fexp10(o1 * M->out_sd[1] + M->out_mu[1]);
             }
         }
         if (accept) {
@@ -406,7 +410,7 @@ hipError_t launch_infer(const InferArgs& a, hipStream_t s)
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ void raw_features(const float* x, float f[kIn])
 {
-    cell_features(x[0], x[1], x[2], x[3], log10f(x[4]), x[5], x[6], x[7], f);
+    cell_features(x[0], x[1], x[2], x[3], flog10(x[4]), x[5], x[6], x[7], f);
 }
 
 __device__ __forceinline__ float raw_baseline(const float* x, float y, int collisional)
@@ -436,7 +440,7 @@ __global__ __launch_bounds__(256) void k_predict(const Model* M, const float* X,
         forward_wave(w, f, o0, o1);
         if (valid) {
             P[(size_t)i * 2] = fminf(fmaxf(xb + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
-            P[(size_t)i * 2 + 1] = x[2] * exp10f(o1 * M->out_sd[1] + M->out_mu[1]);
+            P[(size_t)i * 2 + 1] = x[2] * fexp10(o1 * M->out_sd[1] + M->out_mu[1]);
         }
     }
 }
@@ -460,7 +464,7 @@ __global__ void k_features(const float* X, const float* Y, uint32_t m, float y, 
         const float* x = X + (size_t)i * kIn;
         raw_features(x, F + (size_t)i * kIn);
         Yt[(size_t)i * 2] = Y[(size_t)i * 2] - raw_baseline(x, y, collisional);
-        Yt[(size_t)i * 2 + 1] = log10f(Y[(size_t)i * 2 + 1]) - log10f(x[2]);
+        Yt[(size_t)i * 2 + 1] = flog10(Y[(size_t)i * 2 + 1]) - flog10(x[2]);
     }
 }
 

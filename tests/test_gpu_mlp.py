@@ -88,7 +88,7 @@ def reference_forward(m, X):
     activations (ReLU), FP32 sums; outputs are corrections of the x_HI baseline and the change
     of log10 T. Returns (x_HI', log10 T')."""
     f = np.stack([np.log10(X[:, 0]), X[:, 1], np.log10(X[:, 2]), np.log10(np.maximum(X[:, 3], 1e-30)),
-                  np.log10(X[:, 4]), np.log10(np.maximum(X[:, 5], 1e-40)), X[:, 6], X[:, 7]],
+                  np.log10(X[:, 4]), np.log10(np.maximum(X[:, 5], 1e-35)), X[:, 6], X[:, 7]],
                  axis=1).astype(np.float32)
     x = f32_to_bf16((f - m["in_mu"]) / m["in_sd"])
     h1 = f32_to_bf16(np.maximum(x @ m["w1t"][:, :NIN].T + m["b1"], 0.0))
