@@ -258,15 +258,24 @@ def main():
                "kind": "oracle",
                "sample": f"{idx.size} of {nsrc} sources (every {max(1, nsrc // args.cpu_sample)}th) on the full grid; "
                          f"{r['ledger']['crossings']} crossings in {tc:.1f}s including the FP64 opacity pass"}
-        # the same sample on the GPU, checked against the oracle
-        gs = trace(g, sub.sources, schedule, **tune)
+        # the same sample on the GPU, checked against the oracle, in both traversal precisions
         og = oracle.finalize(state, w.bins, r["J"])[0]
-        gg = gamma.cpu().numpy()
-        errs = []
-        for sp in range(3):
-            m = og[sp] > 1e-6 * og[sp].max()
-            errs.append(float(np.max(np.abs(gg[sp][m] / og[sp][m] - 1))) if m.any() else 0.0)
-        extra["sample_parity"] = {"max_gamma_rel_err": max(errs), "crossings_gpu": gs["crossings"],
+
+        def sample_error(precision):
+            led = ctx.trace(g, sub.sources, w.bins, w.dt, gamma, heat, level0=w.trace["level0"],
+                            rays_per_cell=w.trace["rays_per_cell"], eps_term=w.trace["eps_term"],
+                            precision=precision, schedule="batched")
+            gg = gamma.cpu().numpy()
+            errs = []
+            for sp in range(3):
+                m = og[sp] > 1e-6 * og[sp].max()
+                errs.append(float(np.max(np.abs(gg[sp][m] / og[sp][m] - 1))) if m.any() else 0.0)
+            return max(errs), led["crossings"]
+
+        e_comp, x_comp = sample_error("fp32_comp")
+        e_plain, x_plain = sample_error("fp32_plain")
+        extra["sample_parity"] = {"max_gamma_rel_err": e_comp, "max_gamma_rel_err_fp32_plain": e_plain,
+                                  "crossings_gpu": x_comp, "crossings_gpu_fp32_plain": x_plain,
                                   "crossings_oracle": r["ledger"]["crossings"]}
         log(f"sample parity: {extra['sample_parity']}")
 

@@ -225,3 +225,23 @@ def test_c2_config_parity(arc, ctx):
     assert conservation(g["ledger"]) <= CONSERVATION_TOL
     gp = run_gpu_trace(arc, ctx, w, schedule="plain")
     assert np.array_equal(gp["J"], g["J"])
+
+
+@pytest.mark.parametrize("edges", [(13.6,), (13.6, 24.6), (13.6, 20.0, 24.6, 54.4)], ids=["1bin", "2bins", "4bins"])
+def test_bin_counts_parity(arc, ctx, edges):
+    """Every bin count the library supports (one kernel instantiation each) against the
+    oracle, and the two schedules against each other."""
+    import dataclasses
+
+    w = small_lognormal(shape=(32, 36, 40), n_src=3, seed=40 + len(edges))
+    w = dataclasses.replace(w, bins=W.bins_blackbody(edges=edges))
+    assert len(w.bins["frac"]) == len(edges)
+    g = run_gpu_trace(arc, ctx, w, schedule="batched")
+    p = run_gpu_trace(arc, ctx, w, schedule="plain")
+    o = run_oracle(w)
+    assert max(rate_errors(g, o)) <= GAMMA_REL_TOL
+    assert max(rate_errors(g, o, key="heat")) <= GAMMA_REL_TOL
+    assert conservation(g["ledger"]) <= CONSERVATION_TOL
+    assert np.array_equal(g["J"], p["J"])
+    # FP32 and FP64 may decide a termination differently at the threshold: a few crossings
+    assert abs(g["ledger"]["crossings"] - o["ledger"]["crossings"]) <= 1e-5 * o["ledger"]["crossings"]
