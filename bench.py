@@ -134,7 +134,7 @@ def main():
                     "val_rmse_x": rep["val_rmse_x"], "val_rmse_logt": rep["val_rmse_logt"],
                     "bins_used": rep["bins_used"], "gate_tol": args.gate_tol}
         log(f"learned chemistry: {mlp_info}")
-    chem_kw = dict(w.chem)
+    chem_kw = dict(w.chem, graph=bool(args.graph))
     if net is not None:
         chem_kw.update(mode="mlp_gated", mlp=net, gate_tol=args.gate_tol)
 

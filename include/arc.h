@@ -256,6 +256,8 @@ typedef struct {
     const arc_mlp* mlp;    /* trained network for the MLP modes */
     double gate_tol;       /* MLP_GATED: largest accepted held-out bin error */
     int32_t gate_min_count; /* MLP_GATED: smallest accepted training count per bin */
+    int32_t graph;         /* 1 = record the step's launches in HIP graphs once and replay them
+                              while every launch argument repeats; results are identical to 0 */
 } arc_chem_params;
 
 typedef struct {

@@ -74,7 +74,7 @@ class ChemParams(C.Structure):
     _fields_ = [("isothermal", C.c_int32), ("rates", C.c_int32), ("collisional", C.c_int32),
                 ("alpha_hii", C.c_double), ("eps", C.c_double), ("max_sub", C.c_int32), ("t_floor", C.c_double),
                 ("mode", C.c_int32), ("stream", C.c_void_p), ("mlp", C.c_void_p), ("gate_tol", C.c_double),
-                ("gate_min_count", C.c_int32)]
+                ("gate_min_count", C.c_int32), ("graph", C.c_int32)]
 
 
 class ChemStats(C.Structure):
@@ -256,12 +256,12 @@ class Context:
 
     def chem_step(self, grid, gamma, heat, dt: float, isothermal=0, rates=1, collisional=1, alpha_hii=2.59e-13,
                   eps=0.1, max_sub=100000, t_floor=1.0, mode="plain", stream=None, mlp=None, gate_tol=1e-3,
-                  gate_min_count=16) -> dict:
+                  gate_min_count=16, graph=False) -> dict:
         g = _grid(grid)
         r = Rates(_ptr(gamma), _ptr(heat))
         p = ChemParams(int(isothermal), int(rates), int(collisional), float(alpha_hii), float(eps), int(max_sub),
                        float(t_floor), CHEM_MODE[mode] if isinstance(mode, str) else int(mode), _stream(stream),
-                       mlp._h if mlp is not None else None, float(gate_tol), int(gate_min_count))
+                       mlp._h if mlp is not None else None, float(gate_tol), int(gate_min_count), int(bool(graph)))
         st = ChemStats()
         self._check(lib().arc_chem_step(self._h, C.byref(g), C.byref(r), float(dt), C.byref(p), C.byref(st)))
         return {k: getattr(st, k) for k, _ in ChemStats._fields_}

@@ -63,6 +63,9 @@ struct arc_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<unsigned char> graph_key;
+    // the chemistry step's stages (statistics, network, solver), same scheme
+    hipGraphExec_t cexec[3] = {nullptr, nullptr, nullptr};
+    std::vector<unsigned char> chem_key;
     unsigned long long* sums = nullptr;  // field checksums of the autotuner
     struct Tuned {
         int nx, ny, nz, nb, level0, lmax, precision;
@@ -259,6 +262,8 @@ void arc_destroy(arc_ctx* c)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     for (int i = 0; i < 4; ++i)
         if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+    for (int i = 0; i < 3; ++i)
+        if (c->cexec[i]) (void)hipGraphExecDestroy(c->cexec[i]);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->sums) (void)hipFree(c->sums);
     delete c;
@@ -965,6 +970,64 @@ arc_status arc_healpix_dirs(arc_ctx* c, int32_t level, float* dst, void* stream)
     return ARC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Everything the chemistry step launches with, zero-filled (its bytes key the graphs).
+struct ChemPlan {
+    ChemArgs a;
+    mlp::InferArgs ia;
+    int mode;
+    int cus;
+};
+
+// Stage 0: statistics and the work counter; stage 1 (learned modes): network and gate;
+// stage 2 (plain and gated modes): the sub-cycled solver.
+hipError_t chem_stage(arc_ctx* c, const ChemPlan& P, int stage, hipStream_t st)
+{
+    if (stage == 0) return launch_zero_u64(c->chem_stats, 5, st);
+    if (stage == 1) return P.mode != ARC_CHEM_PLAIN ? mlp::launch_infer(P.ia, st) : hipSuccess;
+    return P.mode != ARC_CHEM_MLP_ONLY ? launch_chem(P.a, P.cus, st) : hipSuccess;
+}
+
+arc_status ensure_chem_graphs(arc_ctx* c, const ChemPlan& P)
+{
+    const unsigned char* key = reinterpret_cast<const unsigned char*>(&P);
+    if (c->cexec[0] && c->chem_key.size() == sizeof P && std::memcmp(c->chem_key.data(), key, sizeof P) == 0)
+        return ARC_OK;
+    for (int i = 0; i < 3; ++i)
+        if (c->cexec[i]) {
+            HIP_TRY(c, hipGraphExecDestroy(c->cexec[i]));
+            c->cexec[i] = nullptr;
+        }
+    c->chem_key.clear();
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    for (int i = 0; i < 3; ++i) {
+        HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t e = chem_stage(c, P, i, c->cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(c, ARC_E_DEVICE, "graph capture of chemistry stage %d: %s", i,
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        const hipError_t e3 = hipGraphInstantiate(&c->cexec[i], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+            c->cexec[i] = nullptr;
+            return fail(c, ARC_E_DEVICE, "graph instantiation of chemistry stage %d: %s", i, hipGetErrorString(e3));
+        }
+    }
+    c->chem_key.assign(key, key + sizeof P);
+    return ARC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, double dt, const arc_chem_params* p,
                          arc_chem_stats* stats)
 {
@@ -988,7 +1051,11 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     if (p->mode == ARC_CHEM_MLP_GATED && !(p->gate_tol >= 0)) return fail(c, ARC_E_RANGE, "gate_tol must be >= 0");
     hipStream_t st = (hipStream_t)p->stream;
     HIP_TRY(c, hipSetDevice(c->device));
-    ChemArgs a{};
+    ChemPlan P;
+    std::memset(&P, 0, sizeof P);
+    P.mode = p->mode;
+    P.cus = c->cus;
+    ChemArgs& a = P.a;
     a.ncell = (uint32_t)((size_t)g->nx * g->ny * g->nz);
     a.y = g->y_he;
     a.n_h = g->n_h;
@@ -1007,10 +1074,8 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
     a.eps = p->eps;
     a.t_floor = p->t_floor;
     a.stats = c->chem_stats;
-    a.mask = nullptr;
-    HIP_TRY(c, launch_zero_u64(c->chem_stats, 5, st));
     a.chunk_counter = (uint32_t*)(c->chem_stats + 4);
-    HIP_TRY(c, hipEventRecord(c->ev[0], st));
+    a.mask = nullptr;
     if (p->mode != ARC_CHEM_PLAIN) {
         const size_t words = ((size_t)a.ncell + 63) / 64;
         if (words > c->reject_cap) {
@@ -1020,7 +1085,7 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
             HIP_TRY(c, hipMalloc((void**)&c->reject, words * sizeof(unsigned long long)));
             c->reject_cap = words;
         }
-        mlp::InferArgs ia{};
+        mlp::InferArgs& ia = P.ia;
         ia.model = p->mlp->model;
         ia.ncell = a.ncell;
         ia.y = a.y;
@@ -1038,14 +1103,21 @@ arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, doub
         ia.t_floor = (float)p->t_floor;
         ia.reject = c->reject;
         ia.collisional = p->rates == 1 ? p->collisional : 0;
-        HIP_TRY(c, mlp::launch_infer(ia, st));
+        if (p->mode == ARC_CHEM_MLP_GATED) a.mask = c->reject;
+    }
+    if (p->graph) {
+        if ((rc = ensure_chem_graphs(c, P)) != ARC_OK) return rc;
+        HIP_TRY(c, hipGraphLaunch(c->cexec[0], st));
+        HIP_TRY(c, hipEventRecord(c->ev[0], st));
+        HIP_TRY(c, hipGraphLaunch(c->cexec[1], st));
         HIP_TRY(c, hipEventRecord(c->ev[2], st));
-        if (p->mode == ARC_CHEM_MLP_GATED) {
-            a.mask = c->reject;
-            HIP_TRY(c, launch_chem(a, st));
-        }
+        HIP_TRY(c, hipGraphLaunch(c->cexec[2], st));
     } else {
-        HIP_TRY(c, launch_chem(a, st));
+        HIP_TRY(c, chem_stage(c, P, 0, st));
+        HIP_TRY(c, hipEventRecord(c->ev[0], st));
+        HIP_TRY(c, chem_stage(c, P, 1, st));
+        HIP_TRY(c, hipEventRecord(c->ev[2], st));
+        HIP_TRY(c, chem_stage(c, P, 2, st));
     }
     HIP_TRY(c, hipEventRecord(c->ev[1], st));
     unsigned long long cs[4];

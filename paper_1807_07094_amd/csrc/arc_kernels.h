@@ -74,6 +74,7 @@ int persistent_max_waves();
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, int nx, int ny, int nbx8, int nby8,
                             uint32_t ncell, long long* dst, hipStream_t s);
-hipError_t launch_chem(const ChemArgs& a, hipStream_t s);
+// cus: compute units of the device (the solver launches resident waves only)
+hipError_t launch_chem(const ChemArgs& a, int cus, hipStream_t s);
 
 }  // namespace arc

@@ -851,14 +851,10 @@ __global__ __launch_bounds__(256) void k_chem(ChemArgs a)
     }
 }
 
-hipError_t launch_chem(const ChemArgs& a, hipStream_t s)
+hipError_t launch_chem(const ChemArgs& a, int cus, hipStream_t s)
 {
     // resident waves only: every wave loops until the chunk counter passes ncell
-    int dev = 0, cus = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    const unsigned blocks = std::max(1u, std::min(grid_for(a.ncell, 256), (unsigned)cus * 8u));
+    const unsigned blocks = std::max(1u, std::min(grid_for(a.ncell, 256), (unsigned)std::max(1, cus) * 8u));
     k_chem<<<blocks, 256, 0, s>>>(a);
     return hipGetLastError();
 }

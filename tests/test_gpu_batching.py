@@ -82,3 +82,30 @@ def test_tuned_schedule_tunes_on_first_use(arc):
         assert tuned["ledger"]["crossings"] == plain["ledger"]["crossings"]
     finally:
         fresh.close()
+
+
+def test_chemistry_graph_replays_equal_eager(arc, ctx):
+    """The plain chemistry step recorded and replayed: every replay from the same state
+    equals the eager step bit for bit, with other GPU work between replays."""
+    import torch
+
+    w = W.lognormal(32, 6, 24)
+    g = arc.device_grid(w.grid)
+    gamma = torch.empty((3,) + w.shape, device="cuda")
+    heat = torch.empty_like(gamma)
+    ctx.trace(g, w.sources, w.bins, w.dt, gamma, heat, level0=w.trace["level0"], eps_term=w.trace["eps_term"])
+    fields = ("x_hi", "x_hei", "x_heii", "temp")
+    start = {k: g[k].clone() for k in fields}
+    eager_stats = ctx.chem_step(g, gamma, heat, w.dt, **w.chem)
+    eager = {k: g[k].clone() for k in fields}
+    for rep in range(3):
+        for k in fields:
+            g[k].copy_(start[k])
+        torch.cuda.synchronize()
+        st = ctx.chem_step(g, gamma, heat, w.dt, graph=True, **w.chem)
+        for k in fields:
+            assert bool((g[k] == eager[k]).all()), (rep, k)
+        assert st["sub_total"] == eager_stats["sub_total"]
+        a = torch.randn(256, 256, device="cuda")
+        float((a @ a).sum())
+        torch.cuda.synchronize()
