@@ -26,10 +26,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # and WRITE_SIZE (x1.0) on this workload, valid for the kernel sources with these digests; with
 # any other sources the figure is stale and the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "bytes_per_crossing": 36.36,
+    "bytes_per_crossing": 36.35,
     "sha256": {
         "paper_1807_07094_amd/csrc/arc_device.h": "804067ef347837df1e09c7fe5a3826d31d4a474d855b69f9803f03f5d8f81e7b",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "1c43738c6d620d242a9b7b58877516bde69a24c3009bc5550b06eeb39e7800e9",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "a135a369edc532e0797cdcb5dfcaa2b6f1f73f9db63bb1ff1356bcc72af996f8",
     },
     "profile": "profiles/hbm_traffic_grf1024_16384src.md",
 }
