@@ -208,7 +208,7 @@ typedef struct arc_mlp arc_mlp;
 typedef struct {
     int32_t epochs;        /* passes over the training samples */
     int32_t batch;         /* minibatch size (multiple of 64 recommended) */
-    double lr;             /* Adam learning rate */
+    double lr;             /* peak Adam learning rate (cosine decay to lr/20 over the run) */
     uint32_t seed;         /* initialisation and shuffling */
     double val_frac;       /* share of the samples held out for the gate (0 < v < 1) */
     void* stream;          /* hipStream_t, NULL = default stream */

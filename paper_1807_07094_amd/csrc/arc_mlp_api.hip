@@ -214,6 +214,7 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
     TRY(hipMalloc((void**)&partial, (size_t)max_waves * kNParams * sizeof(float)));
     guard.ptrs.push_back(partial);
     int step = 0;
+    const double total_steps = (double)p->epochs * (double)((n_train + batch - 1) / batch);
     for (int ep = 0; ep < p->epochs; ++ep) {
         std::shuffle(train.begin(), train.end(), rng);
         TRY(hipMemcpyAsync(idx, train.data(), n_train * sizeof(uint32_t), hipMemcpyHostToDevice, st));
@@ -228,7 +229,10 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
             aa.v = mlp->params + 2 * kNParams;
             aa.partial = partial;
             aa.nwaves = (int)((count + 63) / 64);
-            aa.lr = (float)p->lr;
+            // cosine decay from lr to lr/20 over the run: the late small steps settle the
+            // minibatch noise that a constant rate leaves in the weights
+            const double frac = (double)step / total_steps;
+            aa.lr = (float)(p->lr * (0.05 + 0.95 * 0.5 * (1.0 + std::cos(M_PI * frac))));
             aa.beta1 = 0.9f;
             aa.beta2 = 0.999f;
             aa.eps = 1e-8f;
