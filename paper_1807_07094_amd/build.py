@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(OUT_DIR, "libarc.so")
-SOURCES = ["arc_kernels.hip", "arc_mlp.hip", "arc_api.hip", "arc_mlp_api.hip"]
+SOURCES = ["arc_kernels.hip", "arc_chem.hip", "arc_mlp.hip", "arc_api.hip", "arc_mlp_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -29,6 +29,11 @@ HIPCC_FLAGS = [
     "-Wno-unused-function",
 ]
 
+# per-source additions: the network kernels keep MFMA accumulators in ordinary VGPRs (the
+# activations are consumed by VALU code right away; accumulation registers would need a
+# copy per element)
+EXTRA_FLAGS = {"arc_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
 
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
@@ -42,7 +47,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+        cmd = [hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

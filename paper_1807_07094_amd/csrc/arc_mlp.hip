@@ -191,23 +191,42 @@ __device__ __forceinline__ void load_lds_weights(const Model* M, LdsWeights& L)
     if (threadIdx.x < kOut) L.b3[threadIdx.x] = M->b3[threadIdx.x];
 }
 
-// Hidden layer: bias, ReLU and BF16 rounding of four M-tiles, packed as the two k-steps of
-// the next layer's B operand.
-__device__ __forceinline__ void hidden_to_operand(const f32x4 d[4], const float4* bias, bf16x8 h[2])
+// ReLU of a pair after its BF16 rounding (rounding keeps the sign, so this equals rounding
+// after the ReLU): as 16-bit integers the negative BF16 values, -0 included, are exactly
+// the negative numbers, and one packed integer max clears both halves.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b)
 {
-    const int q = (threadIdx.x & 63) >> 4;
+    const f32x2 p = {a, b};
+    const bf16x2 v = __builtin_convertvector(p, bf16x2);  // one packed round-to-nearest-even
+    const i16x2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2, v), z));
+}
+
+// Hidden layer: ReLU and BF16 rounding of four M-tiles (biases already in the
+// accumulators), packed as the two k-steps of the next layer's B operand (elements 2j and
+// 2j + 1 of an operand are the low and high halves of its word j).
+__device__ __forceinline__ void hidden_to_operand(const f32x4 d[4], bf16x8 h[2])
+{
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
-        const float4 b0 = bias[4 * (2 * s2) + q], b1 = bias[4 * (2 * s2 + 1) + q];
-        h[s2][0] = (__bf16)act(d[2 * s2][0] + b0.x);
-        h[s2][1] = (__bf16)act(d[2 * s2][1] + b0.y);
-        h[s2][2] = (__bf16)act(d[2 * s2][2] + b0.z);
-        h[s2][3] = (__bf16)act(d[2 * s2][3] + b0.w);
-        h[s2][4] = (__bf16)act(d[2 * s2 + 1][0] + b1.x);
-        h[s2][5] = (__bf16)act(d[2 * s2 + 1][1] + b1.y);
-        h[s2][6] = (__bf16)act(d[2 * s2 + 1][2] + b1.z);
-        h[s2][7] = (__bf16)act(d[2 * s2 + 1][3] + b1.w);
+        const f32x4 a = d[2 * s2], b = d[2 * s2 + 1];
+        const u32x4 w = {relu_bf16x2(a[0], a[1]), relu_bf16x2(a[2], a[3]), relu_bf16x2(b[0], b[1]),
+                         relu_bf16x2(b[2], b[3])};
+        h[s2] = __builtin_bit_cast(bf16x8, w);
     }
+}
+
+// Accumulator start of M-tile t: rows 4q..4q+3 of every column carry the biases of hidden
+// units 16t + 4q .. 16t + 4q + 3, so the MFMA adds them.
+__device__ __forceinline__ f32x4 bias_acc(const float4* bias, int t)
+{
+    const float4 b = bias[4 * t + ((threadIdx.x & 63) >> 4)];
+    const f32x4 v = {b.x, b.y, b.z, b.w};
+    return v;
 }
 
 // One tile of 16 cells: x = the layer-1 B operand (lanes with q = 0 hold the 8 standardised
@@ -216,19 +235,18 @@ __device__ __forceinline__ void hidden_to_operand(const f32x4 d[4], const float4
 __device__ __forceinline__ f32x4 forward_tile(const LdsWeights& w, bf16x8 x)
 {
     const int lane = threadIdx.x & 63;
-    const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 d[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) d[t] = mfma(w.frag[t][lane], x, z);
+    for (int t = 0; t < 4; ++t) d[t] = mfma(w.frag[t][lane], x, bias_acc(w.b1, t));
     bf16x8 h[2];
-    hidden_to_operand(d, w.b1, h);
+    hidden_to_operand(d, h);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) d[t] = mfma(w.frag[5 + 2 * t][lane], h[1], mfma(w.frag[4 + 2 * t][lane], h[0], z));
-    hidden_to_operand(d, w.b2, h);
-    f32x4 o = mfma(w.frag[13][lane], h[1], mfma(w.frag[12][lane], h[0], z));
-    o[0] += w.b3[0];
-    o[1] += w.b3[1];
-    return o;
+    for (int t = 0; t < 4; ++t)
+        d[t] = mfma(w.frag[5 + 2 * t][lane], h[1], mfma(w.frag[4 + 2 * t][lane], h[0], bias_acc(w.b2, t)));
+    hidden_to_operand(d, h);
+    const bool q0 = lane < 16;
+    const f32x4 b3 = {q0 ? w.b3[0] : 0.0f, q0 ? w.b3[1] : 0.0f, 0.0f, 0.0f};
+    return mfma(w.frag[13][lane], h[1], mfma(w.frag[12][lane], h[0], b3));
 }
 
 // Forward pass of the 64 cells of a wave, one per lane: f = the lane's standardised
@@ -290,10 +308,9 @@ __device__ __forceinline__ void cell_features(float nh, float x, float T, float 
 // Baseline of x_HI': dx/dt = a (1 - x) - b x with a = alpha_HII(T) n_e and b = Gamma_HI +
 // k_HI(T) n_e held at their start-of-step values (section 2.7 rates), solved exactly:
 // x_base = x_eq + (x - x_eq) exp(-(a + b) dt), x_eq = a / (a + b).
-__device__ __forceinline__ float x_baseline(float nh, float x, float T, float gam, float xheii, float xhei, float dt,
-                                            float y, int collisional)
+__device__ __forceinline__ float x_baseline(const chem::Coef& k, float nh, float x, float gam, float xheii, float xhei,
+                                            float dt, float y, int collisional)
 {
-    const chem::Coef k = chem::coefficients(T);
     const float xheiii = fmaxf(0.0f, 1.0f - xhei - xheii);
     const float ne = nh * ((1.0f - x) + y * (xheii + 2.0f * xheiii));
     const float a = k.a_hii * ne;
@@ -304,10 +321,27 @@ __device__ __forceinline__ float x_baseline(float nh, float x, float T, float ga
     return xeq + (x - xeq) * expf(-lam * dt);
 }
 
-__device__ __forceinline__ void standardise(const Model* M, bool valid, float f[kIn])
+// Reciprocals of the standardisation scales and of the gate ranges, taken once per thread
+// (correctly rounded, as on the host, so that both sides bin and scale identically).
+struct Scales {
+    float isd[kIn];
+    float igate[kGateDims];
+};
+
+__device__ __forceinline__ Scales scales_of(const Model* M)
+{
+    Scales z;
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) z.isd[k] = 1.0f / M->in_sd[k];
+#pragma unroll
+    for (int k = 0; k < kGateDims; ++k) z.igate[k] = 1.0f / (M->hi[k] - M->lo[k]);
+    return z;
+}
+
+__device__ __forceinline__ void standardise(const Model* M, const Scales& z, bool valid, float f[kIn])
 {
 #pragma unroll
-    for (int k = 0; k < kIn; ++k) f[k] = valid ? (f[k] - M->in_mu[k]) / M->in_sd[k] : 0.0f;
+    for (int k = 0; k < kIn; ++k) f[k] = valid ? (f[k] - M->in_mu[k]) * z.isd[k] : 0.0f;
 }
 
 // ---------------------------------------------------------------------------------
@@ -320,6 +354,7 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
     load_lds_weights(M, w);
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    const Scales z = scales_of(M);
     const float dtf = (float)a.dt, ldt = flog10(dtf);
     const float yf = (float)a.y;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -345,7 +380,7 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
             uint32_t bin = 0;
 #pragma unroll
             for (int k = kGateDims - 1; k >= 0; --k) {
-                const float u = (f[k] - M->lo[k]) / (M->hi[k] - M->lo[k]);
+                const float u = (f[k] - M->lo[k]) * z.igate[k];
                 accept = accept && u >= 0.0f && u <= 1.0f;
                 const int b = min(kGate - 1, max(0, (int)(u * kGate)));
                 bin = bin * kGate + (uint32_t)b;
@@ -353,15 +388,17 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
             accept = accept && M->gate_count[bin] >= a.gate_min_count && M->gate_err[bin] <= a.gate_tol;
         }
         float xn = 0.0f, Tn = 0.0f;
+        chem::Coef k{};
         // the network runs only for waves with a cell past the gate bins (wave-uniform branch)
         const uint64_t cand = __ballot(accept);
         if (cand) {
-            standardise(M, valid, f);
+            standardise(M, z, valid, f);
             float o0, o1;
             forward_wave(w, f, o0, o1, cand);
             // the outputs (the baseline only where they can still be used)
             if (accept) {
-                xb = x_baseline(nh, x0, T, gam, xheii, xhei, dtf, M->base_y, M->base_collisional);
+                k = chem::coefficients(T);
+                xb = x_baseline(k, nh, x0, gam, xheii, xhei, dtf, M->base_y, M->base_collisional);
                 xn = fminf(fmaxf(xb + (o0 * M->out_sd[0] + M->out_mu[0]), 0.0f), 1.0f);
                 Tn = T * fexp10(o1 * M->out_sd[1] + M->out_mu[1]);
             }
@@ -377,7 +414,6 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
                     const float nhei = nhe * xhei, nheii = nhe * xheii;
                     const float nheiii = fmaxf(0.0f, nhe - nhei - nheii);
                     const float ne = nh * (1.0f - x0) + nheii + 2.0f * nheiii;
-                    const chem::Coef k = chem::coefficients(T);
                     const float kc = a.collisional ? 1.0f : 0.0f;
                     const float dhei = k.a_heii * ne * nheii - (a.gamma[(size_t)a.ncell + c] + kc * k.k_hei * ne) * nhei;
                     const float dheiii =
@@ -415,7 +451,7 @@ __device__ __forceinline__ void raw_features(const float* x, float f[kIn])
 
 __device__ __forceinline__ float raw_baseline(const float* x, float y, int collisional)
 {
-    return x_baseline(x[0], x[1], x[2], x[3], x[6], x[7], x[4], y, collisional);
+    return x_baseline(chem::coefficients(x[2]), x[0], x[1], x[3], x[6], x[7], x[4], y, collisional);
 }
 
 __global__ __launch_bounds__(256) void k_predict(const Model* M, const float* X, const uint32_t* idx, uint32_t m,
@@ -425,6 +461,7 @@ __global__ __launch_bounds__(256) void k_predict(const Model* M, const float* X,
     load_lds_weights(M, w);
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    const Scales z = scales_of(M);
     for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < m; base += gridDim.x * blockDim.x) {
         const uint32_t i = base + lane;
         const bool valid = i < m;
@@ -435,7 +472,7 @@ __global__ __launch_bounds__(256) void k_predict(const Model* M, const float* X,
             raw_features(x, f);
             xb = raw_baseline(x, M->base_y, M->base_collisional);
         }
-        standardise(M, valid, f);
+        standardise(M, z, valid, f);
         float o0, o1;
         forward_wave(w, f, o0, o1);
         if (valid) {

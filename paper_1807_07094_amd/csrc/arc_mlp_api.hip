@@ -51,7 +51,7 @@ int gate_bin(const float* f, const float* lo, const float* hi)
 {
     int bin = 0;
     for (int k = kGateDims - 1; k >= 0; --k) {
-        const float u = (f[k] - lo[k]) / (hi[k] - lo[k]);
+        const float u = (f[k] - lo[k]) * (1.0f / (hi[k] - lo[k]));  // as the inference kernel bins
         const int b = std::min(kGate - 1, std::max(0, (int)(u * kGate)));
         bin = bin * kGate + b;
     }
@@ -186,7 +186,7 @@ arc_status arc_mlp_train(arc_ctx* ctx, arc_mlp* mlp, const float* X, const float
     // standardised copies for training
     std::vector<float> sF(hF), sY(hY);
     for (size_t i = 0; i < (size_t)m; ++i) {
-        for (int k = 0; k < kIn; ++k) sF[i * kIn + k] = (hF[i * kIn + k] - hm.in_mu[k]) / hm.in_sd[k];
+        for (int k = 0; k < kIn; ++k) sF[i * kIn + k] = (hF[i * kIn + k] - hm.in_mu[k]) * (1.0f / hm.in_sd[k]);
         for (int k = 0; k < kOut; ++k) sY[i * 2 + k] = (hY[i * 2 + k] - hm.out_mu[k]) / hm.out_sd[k];
     }
     TRY(hipMemcpyAsync(F, sF.data(), sF.size() * sizeof(float), hipMemcpyHostToDevice, st));
