@@ -29,7 +29,7 @@ MEASURED_TRAFFIC = {
     "bytes_per_crossing": 36.35,
     "sha256": {
         "paper_1807_07094_amd/csrc/arc_device.h": "804067ef347837df1e09c7fe5a3826d31d4a474d855b69f9803f03f5d8f81e7b",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "a135a369edc532e0797cdcb5dfcaa2b6f1f73f9db63bb1ff1356bcc72af996f8",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "cba9ed26fd5e95d5de4d4a393ce8bc5cab199e7bd830bd9c12f16e45c26d20b2",
     },
     "profile": "profiles/hbm_traffic_grf1024_16384src.md",
 }
