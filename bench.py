@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # and WRITE_SIZE (x1.0) on this workload, valid for the kernel sources with these digests; with
 # any other sources the figure is stale and the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "bytes_per_crossing": 36.35,
+    "bytes_per_crossing": 21.89,
     "sha256": {
         "paper_1807_07094_amd/csrc/arc_device.h": "804067ef347837df1e09c7fe5a3826d31d4a474d855b69f9803f03f5d8f81e7b",
         "paper_1807_07094_amd/csrc/arc_kernels.hip": "cba9ed26fd5e95d5de4d4a393ce8bc5cab199e7bd830bd9c12f16e45c26d20b2",

@@ -113,8 +113,9 @@ typedef struct {
     int32_t tune_refill;   /* batched: refill a wave once this many lanes idle (0 = default) */
     int32_t tune_item_level; /* batched: HEALPix level whose rays become the persistent
                                 launch's work items; earlier levels are traced level by
-                                level (0 = two levels below the first level with 16 items
-                                per wave) */
+                                level (0 = five levels below the first). Lowered while the
+                                rays of that level could exceed a sixth of the device
+                                memory (48-byte records). */
     uint64_t* tree_out;    /* optional device array: every ray traced is appended as
                               (src << 32) | (level << 28) | pixel; NULL = off */
     int64_t tree_cap;      /* capacity of tree_out in entries */
@@ -160,8 +161,8 @@ typedef struct {
     int32_t waves;         /* waves per workgroup of the persistent launch (1, 2, 4, 8) */
     int32_t waves_per_cu;  /* resident waves per compute unit the grid is sized for */
     int32_t refill;        /* refill a wave once this many lanes idle */
-    int32_t item_delta;    /* work-item level minus the first level with >= 16 items per wave
-                              (ARC_SCHED_BATCHED uses 2) */
+    int32_t item_delta;    /* work-item level minus the first level (ARC_SCHED_BATCHED uses 5);
+                              a trace lowers it under the memory bound of tune_item_level */
     double ms_best;        /* trace time of the chosen shape [ms] (tuning sources) */
     double ms_default;     /* trace time of the default shape [ms] (tuning sources) */
     int32_t candidates;    /* shapes timed */

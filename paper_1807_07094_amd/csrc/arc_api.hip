@@ -41,7 +41,8 @@ struct arc_ctx {
     long long dir_off[kMaxLevels] = {0};
     // ray arrays (per-level schedule) and work queue (batched)
     RayRec* rays[2] = {nullptr, nullptr};
-    size_t rays_cap = 0;
+    size_t rcap[2] = {0, 0};   // records each ray buffer holds
+    size_t item_bytes = 0;     // bound on the larger ray buffer of the batched schedule [bytes]
     RayRec* spill = nullptr;
     size_t spill_entries = 0;
     // small device scalars
@@ -235,6 +236,7 @@ arc_status arc_create(int32_t device, arc_ctx** out)
         return ARC_E_DEVICE;
     }
     c->cus = prop.multiProcessorCount;
+    c->item_bytes = prop.totalGlobalMem / 6;
     bool ok = hipMalloc((void**)&c->counters, kNumCounters * sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc((void**)&c->acc, 8 * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&c->u32, 4 * sizeof(uint32_t)) == hipSuccess &&
@@ -292,7 +294,7 @@ struct TracePlan {
     // batched schedule
     int waves, blocks, refill, litem;
     double n_roots;
-    size_t cap;
+    size_t cap[2];  // records of rays0 / rays1
     uint32_t spill_cap;
     RayRec* rays0;
     RayRec* rays1;
@@ -461,41 +463,46 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     return ARC_OK;
 }
 
-// Default depth of the work items below the first level with >= 16 items per wave: two
-// levels deeper (>= 256 items per wave) shortens the tail of the persistent launch, where
-// the last large subtrees run on few waves (1024^3 x 16384 sources: 2030 -> 1820 ms).
-constexpr int kDefaultItemDelta = 2;
+// Default work-item level: five levels below the first. The levels above it are traced
+// level by level (all rays of a level in one launch, no stacks); below it a subtree is
+// small enough for its wave's LDS stack, so rays seldom spill to memory (1024^3 x 16384
+// sources: item level 4 -> 6 took the persistent launch from 1440 to 990 ms and the spills
+// from 1.4e8 to 4e5). Lowered while the larger ray buffer would exceed item_bytes.
+constexpr int kDefaultItemDepth = 5;
 
-// Launch shape of the batched schedule and the buffers it needs. item_delta moves the
-// work-item level from the first level with >= 16 items per wave.
-arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int refill, int item_level, int item_delta)
+// Records of a ray buffer, without keeping its contents.
+hipError_t grow_rays(arc_ctx* c, int i, size_t n)
+{
+    size_t bytes = c->rcap[i] * sizeof(RayRec);
+    const hipError_t e = grow(&c->rays[i], &bytes, n * sizeof(RayRec));
+    c->rcap[i] = bytes / sizeof(RayRec);
+    return e;
+}
+
+// Launch shape of the batched schedule and the buffers it needs. item_level: the HEALPix
+// level whose rays are the persistent launch's work items (0: the default depth); it is
+// clamped to [level0, lmax] and to the memory bound.
+arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int refill, int item_level)
 {
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(c, ARC_E_ARG, "tune_waves must be 1, 2, 4 or 8");
     if (blocks < 1) return fail(c, ARC_E_ARG, "tune_blocks must be >= 1");
     const int level0 = P.A.level0, lmax = P.lmax;
     const uint32_t npix0 = 12u << (2 * level0);
     const double n_roots = (double)P.nsrc * npix0;
-    int litem = level0;
-    if (item_level > 0) {
-        litem = std::max(level0, std::min(lmax, item_level));
-    } else {
-        const double want = 16.0 * blocks * waves;
-        while (litem < lmax && n_roots * std::ldexp(1.0, 2 * (litem - level0)) < want &&
-               n_roots * std::ldexp(1.0, 2 * (litem + 1 - level0)) <= (double)(1u << 26))
-            ++litem;
-        litem = std::max(level0, std::min(lmax, litem + item_delta));
-        while (litem > level0 && n_roots * std::ldexp(1.0, 2 * (litem - level0)) > (double)(1u << 27)) --litem;
-    }
-    const double max_items = n_roots * std::ldexp(1.0, 2 * (litem - level0));
-    if (max_items > (double)0xFFFFFFF0u) return fail(c, ARC_E_UNSUPPORTED, "too many work items");
-    const size_t cap = std::max<size_t>(1, (size_t)max_items);
-    if (cap > c->rays_cap) {
-        size_t cap_bytes = c->rays_cap * sizeof(RayRec);
-        size_t cap2 = cap_bytes;
-        HIP_TRY(c, grow(&c->rays[0], &cap_bytes, cap * sizeof(RayRec)));
-        HIP_TRY(c, grow(&c->rays[1], &cap2, cap * sizeof(RayRec)));
-        c->rays_cap = cap;
-    }
+    // rays of level l at most (every ray reaches it)
+    auto rays_at = [&](int l) { return n_roots * std::ldexp(1.0, 2 * (l - level0)); };
+    int litem = item_level > 0 ? item_level : level0 + kDefaultItemDepth;
+    litem = std::max(level0, std::min(lmax, litem));
+    while (litem > level0 &&
+           (rays_at(litem) > (double)0xFFFFFFF0u || rays_at(litem) * sizeof(RayRec) > (double)c->item_bytes))
+        --litem;
+    if (rays_at(litem) > (double)0xFFFFFFF0u) return fail(c, ARC_E_UNSUPPORTED, "too many work items");
+    // buffer b holds the levels l with (l - level0) % 2 == b: the count of its deepest one
+    size_t need[2] = {1, 1};
+    for (int l = level0; l <= litem; ++l)
+        need[(l - level0) & 1] = std::max(need[(l - level0) & 1], (size_t)rays_at(l));
+    for (int i = 0; i < 2; ++i)
+        if (need[i] > c->rcap[i]) HIP_TRY(c, grow_rays(c, i, need[i]));
     const uint32_t spill_cap = 4096;
     const size_t spill_need = (size_t)blocks * waves * spill_cap;
     if (spill_need > c->spill_entries) {
@@ -508,7 +515,8 @@ arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int re
     P.refill = std::max(1, std::min(64, refill));
     P.litem = litem;
     P.n_roots = n_roots;
-    P.cap = cap;
+    P.cap[0] = c->rcap[0];
+    P.cap[1] = c->rcap[1];
     P.spill_cap = spill_cap;
     P.rays0 = c->rays[0];
     P.rays1 = c->rays[1];
@@ -548,8 +556,9 @@ hipError_t enqueue_levels(const TracePlan& P, hipStream_t st)
         uint32_t* cin = cnt + ((l - P.A.level0) & 1);
         uint32_t* cout = cnt + ((l - P.A.level0 + 1) & 1);
         if ((e = launch_set_u32(cout, 0u, st)) != hipSuccess) return e;
-        if ((e = launch_trace_rays(P.A, P.precision, r[cur], cin, (uint32_t)bound, r[1 - cur], cout, (uint32_t)P.cap,
-                                   st)) != hipSuccess)
+        const uint32_t out_cap = (uint32_t)std::min<size_t>(P.cap[1 - cur], 0xFFFFFFF0u);
+        if ((e = launch_trace_rays(P.A, P.precision, r[cur], cin, (uint32_t)bound, r[1 - cur], cout, out_cap, st)) !=
+            hipSuccess)
             return e;
         bound *= 4;
         cur = 1 - cur;
@@ -576,18 +585,13 @@ arc_status run_plain(arc_ctx* c, const TracePlan& P, hipStream_t st)
     const uint32_t npix0 = 12u << (2 * P.A.level0);
     for (int si = 0; si < P.nsrc; ++si) {
         size_t n = npix0;
-        if (4 * n > c->rays_cap) {
-            size_t cap_bytes = c->rays_cap * sizeof(RayRec);
-            size_t cap2 = cap_bytes;
-            HIP_TRY(c, grow(&c->rays[0], &cap_bytes, 4 * n * sizeof(RayRec)));
-            HIP_TRY(c, grow(&c->rays[1], &cap2, 4 * n * sizeof(RayRec)));
-            c->rays_cap = 4 * n;
-        }
+        for (int i = 0; i < 2; ++i)
+            if (4 * n > c->rcap[i]) HIP_TRY(c, grow_rays(c, i, 4 * n));
         HIP_TRY(c, launch_seed_roots((uint32_t)si, 1, P.A.level0, nullptr, c->rays[0], st));
         int cur = 0;
         while (n > 0) {
             const size_t need = 4 * n;
-            if (need > c->rays_cap) {
+            if (need > std::min(c->rcap[0], c->rcap[1])) {
                 // grow both arrays, keeping the current level's rays
                 RayRec* a = nullptr;
                 RayRec* bb = nullptr;
@@ -601,11 +605,11 @@ arc_status run_plain(arc_ctx* c, const TracePlan& P, hipStream_t st)
                 c->rays[0] = a;
                 c->rays[1] = bb;
                 cur = 0;
-                c->rays_cap = need;
+                c->rcap[0] = c->rcap[1] = need;
             }
             HIP_TRY(c, launch_set_u32(c->u32, 0u, st));
             HIP_TRY(c, launch_trace_rays(P.A, P.precision, c->rays[cur], nullptr, (uint32_t)n, c->rays[1 - cur], c->u32,
-                                         (uint32_t)c->rays_cap, st));
+                                         (uint32_t)std::min<size_t>(c->rcap[1 - cur], 0xFFFFFFF0u), st));
             uint32_t nn = 0;
             HIP_TRY(c, hipMemcpyAsync(&nn, c->u32, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             HIP_TRY(c, hipStreamSynchronize(st));
@@ -786,7 +790,7 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
         const int waves = p->tune_waves > 0 ? p->tune_waves : 4;
         const int blocks = p->tune_blocks > 0 ? p->tune_blocks : std::max(1, c->cus * (16 / std::max(1, waves)));
         const int refill = p->tune_refill > 0 ? p->tune_refill : 8;
-        if ((rc = shape_batched(c, P, waves, blocks, refill, p->tune_item_level, kDefaultItemDelta)) != ARC_OK)
+        if ((rc = shape_batched(c, P, waves, blocks, refill, p->tune_item_level)) != ARC_OK)
             return rc;
     } else if (p->schedule == ARC_SCHED_BATCHED_TUNED) {
         const arc_tune_result* t = find_tuned(c, g, P);
@@ -806,7 +810,7 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
             if ((rc = plan_trace(c, g, s, b, dt, p, out, P)) != ARC_OK) return rc;
         }
         const int blocks = std::max(1, c->cus * t->waves_per_cu / t->waves);
-        if ((rc = shape_batched(c, P, t->waves, blocks, t->refill, 0, t->item_delta)) != ARC_OK) return rc;
+        if ((rc = shape_batched(c, P, t->waves, blocks, t->refill, P.A.level0 + t->item_delta)) != ARC_OK) return rc;
     }
     return run_trace(c, P, s, dt, p->schedule, p->graph != 0, st, ledger);
 }
@@ -845,7 +849,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
     // time one shape twice; check its field against the first shape's
     auto time_shape = [&](const arc_tune_result& t, double* ms_out) -> arc_status {
         const int blocks = std::max(1, c->cus * t.waves_per_cu / t.waves);
-        arc_status r2 = shape_batched(c, P, t.waves, blocks, t.refill, 0, t.item_delta);
+        arc_status r2 = shape_batched(c, P, t.waves, blocks, t.refill, P.A.level0 + t.item_delta);
         if (r2 != ARC_OK) return r2;
         double best = INFINITY;
         for (int rep = 0; rep < 2; ++rep) {
@@ -875,7 +879,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
     best.waves = 4;
     best.waves_per_cu = 16;
     best.refill = 8;
-    best.item_delta = kDefaultItemDelta;
+    best.item_delta = kDefaultItemDepth;
     double ms_best;
     if ((rc = time_shape(best, &ms_best)) != ARC_OK) return rc;
     const double ms_default = ms_best;
@@ -889,9 +893,9 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
         }
         return ARC_OK;
     };
-    // (1) work-item level: the deepest subtree roots first matter most
+    // (1) work-item level (levels below the first; the run clamps it to the memory bound)
     const arc_tune_result base1 = best;
-    for (int d : {0, 1, 3, 4}) {
+    for (int d : {2, 3, 4, 6, 7}) {
         arc_tune_result t = base1;
         t.item_delta = d;
         if ((rc = consider(t)) != ARC_OK) return rc;
