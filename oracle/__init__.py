@@ -51,7 +51,7 @@ class Bins(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("level0", C.c_int32), ("max_level", C.c_int32), ("rays_per_cell", C.c_double),
-                ("eps_term", C.c_double)]
+                ("eps_term", C.c_double), ("correction", C.c_int32)]
 
 
 class Ledger(C.Structure):
@@ -173,7 +173,7 @@ def trace(grid: dict, sources: dict, bins: dict, params: dict, tree_cap: int = 0
     keep += [pos, ndot]
     s = Sources(ndot.size, _p(pos), _p(ndot))
     p = Params(int(params["level0"]), int(params.get("max_level", -1)), float(params["rays_per_cell"]),
-               float(params["eps_term"]))
+               float(params["eps_term"]), int(params.get("correction", 0)))
     shape = (g.nz, g.ny, g.nx)
     J = np.empty((b.nbins,) + shape, np.float64)
     gdir = np.empty((3,) + shape, np.float64) if direct else None

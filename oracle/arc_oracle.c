@@ -39,6 +39,15 @@
  *   - Every geometric decision is made exactly: positions lie on a 2^-12 lattice and
  *     directions and split radii are floats, so every product compared below has at
  *     most 48 significant bits and is exact in double.
+ *   - Geometric correction (section 2.5, optional): D_edge is the distance from the
+ *     midpoint of the segment to the nearest face of its cell and L_Pix the width of
+ *     the ray's pixel there, r_mid sqrt(4 pi / N_pix). f_c scales everything the
+ *     crossing deposits in its cell (the termination remainder included). With the
+ *     secondary correction the removed share goes to the neighbour across that face,
+ *     scaled by the ratio of the two cells' opacities in the bin (eq:correction2's
+ *     absorber ratio, read as a density ratio, per bin), which conserves photons; if
+ *     that neighbour is outside the grid or has no opacity in the bin, the share stays.
+ *     Ties between faces go to the lower axis, then to the lower face.
  */
 #include "arc_oracle.h"
 
@@ -298,10 +307,67 @@ static int push(stack_t_* s, const ray_t* r)
 /* g(x) = (1 - e^-x) / x, the mean attenuation over a segment of optical depth x. */
 static double mean_atten(double x) { return x > 0 ? -expm1(-x) / x : 1.0; }
 
+/* Section 2.5, eq:correction: the share f_c of a crossing's photons its own cell keeps,
+ * for a segment of cell c between path lengths t0 and t1 of a level-`level` ray. Also the
+ * neighbour across the face nearest to the segment's midpoint (*nb = -1: none inside). */
+static double orc_correction(const walk_t* w, double t0, double t1, int32_t level, int mode, int32_t nx,
+                             int32_t ny, int32_t nz, int64_t* nb)
+{
+    const double tm = 0.5 * (t0 + t1);
+    const double lpix = tm * sqrt(4.0 * ORC_PI / (double)orc_npix(level));
+    double dmin = INFINITY;
+    int axis = 0, side = 0;
+    for (int i = 0; i < 3; ++i) {
+        const double m = w->xs[i] + tm * w->d[i];
+        const double lo = m - (double)w->c[i], hi = (double)(w->c[i] + 1) - m;
+        const double di = lo <= hi ? lo : hi;
+        if (di < dmin) {
+            dmin = di;
+            axis = i;
+            side = lo <= hi ? -1 : 1;
+        }
+    }
+    *nb = -1;
+    if (!(dmin < 0.5 * lpix)) return 1.0;
+    double fc = 0.5 + dmin / lpix;
+    if (mode == 3) fc *= fc;
+    if (mode == 2) {
+        int64_t c[3] = {w->c[0], w->c[1], w->c[2]};
+        c[axis] += side;
+        const int64_t n[3] = {nx, ny, nz};
+        if (c[axis] < 0 || c[axis] >= n[axis]) return 1.0;  /* no neighbour: the share stays */
+        *nb = c[0] + (int64_t)nx * (c[1] + (int64_t)ny * c[2]);
+    }
+    return fc;
+}
+
+/* Field deposit of amount a (photons per unit opacity) of bin k into cell c, split by the
+ * geometric correction: f_c a stays; with a neighbour, (1 - f_c) a kappa_c / kappa_nb goes
+ * there (the same photons, absorbed at the neighbour's opacity). */
+static void orc_deposit(double* J, const double* kappa, int64_t ncell, int k, int64_t c, double a, double fc,
+                        int64_t nb)
+{
+    if (fc >= 1.0) {
+        J[(int64_t)k * ncell + c] += a;
+        return;
+    }
+    const double kc = kappa[(int64_t)k * ncell + c];
+    const double kn = nb >= 0 ? kappa[(int64_t)k * ncell + nb] : 0.0;
+    if (nb >= 0 && kn > 0) {
+        J[(int64_t)k * ncell + c] += fc * a;
+        J[(int64_t)k * ncell + nb] += (1.0 - fc) * a * (kc / kn);
+    } else if (nb >= 0) {
+        J[(int64_t)k * ncell + c] += a;  /* no absorber next door: the share stays */
+    } else {
+        J[(int64_t)k * ncell + c] += fc * a;
+    }
+}
+
 int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, const orc_params* p,
                   double* J, double* gdir, uint64_t* tree, int64_t tree_cap, orc_ledger* led)
 {
     if (!g || !s || !b || !p || !J || !led) return -1;
+    if (p->correction < 0 || p->correction > 3 || (p->correction && gdir)) return -1;
     if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || b->nbins <= 0 || b->nbins > ORC_MAXB) return -1;
     if (p->level0 < 0 || p->rays_per_cell <= 0) return -1;
     const int nb = b->nbins;
@@ -372,11 +438,14 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
                 const double ds = tn - w.t;
                 const int64_t c = w.c[0] + (int64_t)nx * (w.c[1] + (int64_t)ny * w.c[2]);
                 led->crossings++;
+                int64_t cnb = -1;
+                const double fc = p->correction ? orc_correction(&w, w.t, tn, r.level, p->correction, nx, ny, nz, &cnb)
+                                                : 1.0;
                 for (int k = 0; k < nb; ++k) {
                     const double kap = kappa[(int64_t)k * ncell + c];
                     dtau[k] = kap * ds;
                     const double lost = -expm1(-dtau[k]);        /* 1 - e^-dtau */
-                    J[(int64_t)k * ncell + c] += P[k] * ds * mean_atten(dtau[k]);
+                    orc_deposit(J, kappa, ncell, k, c, P[k] * ds * mean_atten(dtau[k]), fc, cnb);
                     led->absorbed_trace += P[k] * lost;
                     if (gdir && dtau[k] > 0) {
                         /* eq:ion with the absorbed photons split by species optical depth */
@@ -397,7 +466,7 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
                 if (term) {
                     for (int k = 0; k < nb; ++k) {
                         const double kap = kappa[(int64_t)k * ncell + c];
-                        J[(int64_t)k * ncell + c] += P[k] / kap;
+                        orc_deposit(J, kappa, ncell, k, c, P[k] / kap, fc, cnb);
                         led->absorbed_trace += P[k];
                         if (gdir) {
                             const double nh = g->n_h[c];

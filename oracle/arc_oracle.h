@@ -52,6 +52,9 @@ typedef struct {
     int32_t max_level;       /* <0: smallest level whose split radius exceeds the box diagonal */
     double rays_per_cell;    /* Phi: rays per cell-face area at the split radius */
     double eps_term;         /* terminate when every bin is attenuated below this; 0 = never */
+    int32_t correction;      /* geometric correction (section 2.5): 0 none; 1 f_c (eq:correction);
+                                2 f_c plus the photon-conserving secondary deposit
+                                (eq:correction2); 3 f_c squared. Not with the direct rates. */
 } orc_params;
 
 typedef struct {
