@@ -105,7 +105,7 @@ def hand_field(shape, xs, kappa, S, mode):
                     best = (di, i, side)
             dmin, axis, side = best
             lp = tm * lpix_per_r
-            fc = 1.0 if dmin >= 0.5 * lp else 0.5 + dmin / lp
+            fc = 1.0 if mode == 0 or dmin >= 0.5 * lp else 0.5 + dmin / lp
             if mode == 3:
                 fc = fc * fc
             a = P * s * (-math.expm1(-kappa * s) / (kappa * s))
