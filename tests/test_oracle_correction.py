@@ -61,6 +61,18 @@ def test_secondary_correction_conserves_photons():
     assert led1["absorbed_trace"] == pytest.approx(led2["absorbed_trace"], rel=1e-12)
 
 
+def test_secondary_correction_conserves_photons_across_a_sharp_front():
+    """Neutral gas next to gas ionised to 1e-4: the neighbours' opacity ratios span both
+    sides of the 1/16 bound, and photons are conserved either way."""
+    w = lognormal(shape=(20, 20, 20), n_src=2, seed=9)
+    w.grid["x_hi"] = w.grid["x_hi"].copy()
+    w.grid["x_hi"][:, :, 10:] = 1e-4
+    r2, absorbed2 = run(w, 2)
+    r0, _ = run(w, 0)
+    assert absorbed2 == pytest.approx(r2["ledger"]["absorbed_trace"], rel=1e-10)
+    assert np.abs(r2["J"] - r0["J"]).max() > 0
+
+
 def test_secondary_correction_moves_but_keeps_the_total_in_uniform_gas():
     """Equal opacities: the moved share arrives unscaled, so the summed field is the
     uncorrected one while its distribution changes."""
