@@ -124,7 +124,24 @@ typedef struct {
                               once and replay them while every launch argument repeats
                               (same grid, buffers, sources' fixed-point scales, shape);
                               results are identical to 0 */
+    int32_t correction;    /* geometric correction (section 2.5), ARC_CORR_*; needs
+                              ARC_PREC_FP32_COMP (else ARC_E_UNSUPPORTED) */
 } arc_trace_params;
+
+/* Geometric correction (section 2.5). D_edge: distance from a crossing's midpoint to the
+ * nearest face of its cell; L_Pix: the ray's pixel width there, r sqrt(4 pi / N_pix). The
+ * cell keeps f_c = 1/2 + D_edge / L_Pix of the crossing's photons when D_edge < L_Pix / 2
+ * (eq:correction). ARC_CORR_CONSERVING also deposits the rest in the neighbour across that
+ * face, at the neighbour's opacity (eq:correction2, the absorber ratio taken per bin as the
+ * opacity ratio), so photons are conserved; the cell keeps the share when that neighbour is
+ * outside the grid or has less than 1/16 of its opacity in the bin. Faces within 1e-9
+ * cell of each other count as tied (lower axis, then lower face). The other two modes
+ * drop the removed share. With ARC_CORR_CONSERVING the fixed-point unit is 49 times
+ * coarser (a cell may also receive shares from its six neighbours). */
+#define ARC_CORR_NONE 0
+#define ARC_CORR_FC 1           /* f_c alone */
+#define ARC_CORR_CONSERVING 2   /* f_c plus the secondary deposit: the paper's choice */
+#define ARC_CORR_FC_SQUARED 3   /* f_c squared alone */
 
 /* Rates out: device pointers, caller-owned, each [3][ncell] (HI, HeI, HeII). */
 typedef struct {

@@ -48,8 +48,8 @@
  *     absorber ratio, read as a density ratio, per bin), which conserves photons; if
  *     that neighbour is outside the grid or has less than 1/16 of the cell's opacity in
  *     the bin (a bound that keeps the fixed-point field of the GPU library finite; it
- *     also conserves photons), the share stays. Ties between faces go to the lower axis,
- *     then to the lower face.
+ *     also conserves photons), the share stays. Faces within 1e-9 cell of each other
+ *     count as tied; ties go to the lower axis, then to the lower face.
  */
 #include "arc_oracle.h"
 
@@ -60,6 +60,9 @@
 #define ORC_PI 3.14159265358979323846
 #define ORC_MAXB 8
 #define ORC_DTAU_TERM_MIN 0.01
+/* Face distances that agree within this many cells count as tied (symmetric geometries
+ * tie exactly, and the last bits of a midpoint depend on how its path length is summed). */
+#define ORC_FACE_TIE 1e-9
 
 static const double KB_ERG = 1.380649e-16;     /* Boltzmann constant [erg/K] */
 static const double EV_ERG = 1.602176634e-12;  /* electron volt [erg] */
@@ -322,11 +325,12 @@ static double orc_correction(const walk_t* w, double t0, double t1, int32_t leve
     for (int i = 0; i < 3; ++i) {
         const double m = w->xs[i] + tm * w->d[i];
         const double lo = m - (double)w->c[i], hi = (double)(w->c[i] + 1) - m;
-        const double di = lo <= hi ? lo : hi;
-        if (di < dmin) {
+        const int upper = hi < lo - ORC_FACE_TIE;
+        const double di = upper ? hi : lo;
+        if (di < dmin - ORC_FACE_TIE) {
             dmin = di;
             axis = i;
-            side = lo <= hi ? -1 : 1;
+            side = upper ? 1 : -1;
         }
     }
     *nb = -1;

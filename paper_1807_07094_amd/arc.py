@@ -20,6 +20,7 @@ STATUS = {0: "ARC_OK", -1: "ARC_E_ARG", -2: "ARC_E_RANGE", -3: "ARC_E_NOMEM", -4
           -5: "ARC_E_OVERFLOW", -6: "ARC_E_QUEUE", -7: "ARC_E_UNSUPPORTED", -8: "ARC_E_MISMATCH"}
 PREC = {"fp32_comp": 0, "fp32_plain": 1}
 SCHED = {"plain": 0, "batched": 1, "batched_tuned": 2}
+CORR = {"none": 0, "fc": 1, "conserving": 2, "fc_squared": 3}
 
 
 class ArcError(RuntimeError):
@@ -49,7 +50,8 @@ class TraceParams(C.Structure):
                 ("eps_term", C.c_double), ("precision", C.c_int32), ("schedule", C.c_int32),
                 ("stream", C.c_void_p), ("tune_waves", C.c_int32), ("tune_blocks", C.c_int32),
                 ("tune_refill", C.c_int32), ("tune_item_level", C.c_int32), ("tree_out", C.c_void_p),
-                ("tree_cap", C.c_int64), ("u_j_override", C.c_double), ("graph", C.c_int32)]
+                ("tree_cap", C.c_int64), ("u_j_override", C.c_double), ("graph", C.c_int32),
+                ("correction", C.c_int32)]
 
 
 class TuneResult(C.Structure):
@@ -200,7 +202,7 @@ class Context:
 
     @staticmethod
     def _trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term, precision, schedule, stream,
-                    tree, tune_waves, tune_blocks, tune_refill, tune_item_level, u_j_override, graph):
+                    tree, tune_waves, tune_blocks, tune_refill, tune_item_level, u_j_override, graph, correction=0):
         g = _grid(grid)
         pos = np.ascontiguousarray(sources["pos"], np.float64).reshape(-1, 3)
         ndot = np.ascontiguousarray(sources["ndot"], np.float64).reshape(-1)
@@ -214,17 +216,20 @@ class Context:
                         PREC[precision] if isinstance(precision, str) else int(precision),
                         SCHED[schedule] if isinstance(schedule, str) else int(schedule), _stream(stream),
                         int(tune_waves), int(tune_blocks), int(tune_refill), int(tune_item_level), _ptr(tree),
-                        int(tree.numel()) if tree is not None else 0, float(u_j_override), int(bool(graph)))
+                        int(tree.numel()) if tree is not None else 0, float(u_j_override), int(bool(graph)),
+                        CORR[correction] if isinstance(correction, str) else int(correction))
         # the host arrays must outlive the call: keep them with the structures
         return g, s, b, p, (pos, ndot, frac, e, sig, thr)
 
     def trace(self, grid, sources: dict, bins: dict, dt: float, gamma, heat, level0=1, rays_per_cell=4.0,
               max_level=-1, eps_term=1e-6, precision="fp32_comp", schedule="batched", stream=None, tree=None,
-              tune_waves=0, tune_blocks=0, tune_refill=0, tune_item_level=0, u_j_override=0.0, graph=False) -> dict:
-        """arc_trace. gamma/heat: device float32 tensors of shape [3, nz, ny, nx]."""
+              tune_waves=0, tune_blocks=0, tune_refill=0, tune_item_level=0, u_j_override=0.0, graph=False,
+              correction="none") -> dict:
+        """arc_trace. gamma/heat: device float32 tensors of shape [3, nz, ny, nx]. correction:
+        "none", "fc", "conserving" or "fc_squared" (section 2.5)."""
         g, s, b, p, _keep = self._trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term,
                                              precision, schedule, stream, tree, tune_waves, tune_blocks, tune_refill,
-                                             tune_item_level, u_j_override, graph)
+                                             tune_item_level, u_j_override, graph, correction)
         r = Rates(_ptr(gamma), _ptr(heat))
         led = Ledger()
         self._check(lib().arc_trace(self._h, C.byref(g), C.byref(s), C.byref(b), float(dt), C.byref(p),

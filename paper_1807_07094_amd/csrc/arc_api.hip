@@ -325,6 +325,10 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     if (lmax > 12) return fail(c, ARC_E_UNSUPPORTED, "max_level %d > 12 (pixel ids are 28-bit)", lmax);
     if (!(p->u_j_override >= 0)) return fail(c, ARC_E_ARG, "u_j_override must be >= 0");
     if (p->tree_out && p->tree_cap < 0) return fail(c, ARC_E_ARG, "tree_cap < 0");
+    if (p->correction < ARC_CORR_NONE || p->correction > ARC_CORR_FC_SQUARED)
+        return fail(c, ARC_E_ARG, "bad correction mode %d", p->correction);
+    if (p->correction != ARC_CORR_NONE && p->precision != ARC_PREC_FP32_COMP)
+        return fail(c, ARC_E_UNSUPPORTED, "the geometric correction needs ARC_PREC_FP32_COMP");
 
     hipStream_t st = (hipStream_t)p->stream;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -347,12 +351,15 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     // Fixed-point unit per bin. One source deposits at most sqrt(3) S_b into a cell
     // (the photon rate through any sphere is at most S_b and a cell is at most sqrt(3)
     // long), plus a remainder below eps_term S_b sqrt(3) / 0.01 on termination. The sum
-    // over sources therefore stays below 2^62 units.
+    // over sources therefore stays below 2^62 units. With the conserving geometric
+    // correction a cell also receives at most half of each neighbour's crossing, times at
+    // most 16 (the opacity-ratio bound), from each of its six neighbours: 1 + 6 * 8 = 49.
     for (int k = 0; k < kMaxBins; ++k) P.uj[k] = 1.0;
+    const double corr_factor = p->correction == ARC_CORR_CONSERVING ? 49.0 : 1.0;
     for (int i = 0; i < s->n; ++i) P.sum_ndot += s->ndot[i];
     for (int k = 0; k < nb; ++k) {
         const double bound = (std::sqrt(3.0) + p->eps_term * std::sqrt(3.0) / (double)kDtauTermMin) * P.sum_ndot *
-                             b->frac[k] * (1.0 + 1e-6);
+                             b->frac[k] * (1.0 + 1e-6) * corr_factor;
         const double need = bound / 4611686018427387904.0;  // 2^62
         if (p->u_j_override > 0) {
             if (p->u_j_override < need)
@@ -434,6 +441,7 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     A.counters = c->counters;
     A.tree = (unsigned long long*)p->tree_out;
     A.tree_cap = p->tree_out ? p->tree_cap : 0;
+    A.corr = p->correction;
 
     FinalizeArgs& fa = P.fa;
     fa.nb = nb;

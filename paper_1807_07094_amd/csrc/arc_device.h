@@ -92,6 +92,7 @@ struct TraceArgs {
     unsigned long long* counters;  // [kNumCounters]
     unsigned long long* tree;  // optional record of every ray traced
     long long tree_cap;
+    int corr;                  // geometric correction: 0 none, 1 f_c, 2 f_c + secondary, 3 f_c^2
 };
 
 // Per-lane ray state. Along axis i the ray meets its next cell boundary at
@@ -245,7 +246,9 @@ __device__ __forceinline__ bool ray_init(const TraceArgs& A, const Rec& r, Ray<N
         ray.e[i] = fabsf(d[i]);
         ray.ie[i] = d[i] != 0.0f ? __builtin_amdgcn_rcpf(ray.e[i]) : 0.0f;
         ray.step[i] = d[i] > 0.0f ? 1 : (d[i] < 0.0f ? -1 : 0);
-        ray.a[i] = d[i] > 0.0f ? (float)(c + 1) - xs[i] : (d[i] < 0.0f ? xs[i] - (float)c : 1.0f);
+        // d_i = 0: the distance to the upper face (no boundary is met along this axis; the
+        // geometric correction reads the position from it)
+        ray.a[i] = d[i] < 0.0f ? xs[i] - (float)c : (float)(c + 1) - xs[i];
         const int n = i == 0 ? A.nx : (i == 1 ? A.ny : A.nz);
         inside = inside && c >= 0 && c < n;
         ray.ix[i] = inside ? axis_term(A, i, c) : 0u;
@@ -279,7 +282,61 @@ struct Seg {
     uint32_t cell;
     float ds;
     int event;
+    uint32_t nb;  // geometric correction: neighbour that receives the moved share (kNoCell: none)
+    float fc;     // geometric correction: share the cell keeps (1: uncorrected)
 };
+
+constexpr double kSqrtPiOver3 = 1.0233267079464885;  // width of a level-0 pixel per unit radius
+// Face distances within this many cells count as tied: symmetric geometries tie exactly,
+// and the last bits of a midpoint depend on how its path length was summed.
+constexpr double kFaceTie = 1e-9;
+
+// Geometric correction of the segment [t, t_next) in the ray's current cell (section 2.5,
+// eq:correction): D_edge is the distance from the segment's midpoint to the nearest face of
+// the cell, L_Pix the width of the ray's pixel there (r sqrt(4 pi / N_pix)); the cell keeps
+// f_c = 1/2 + D_edge / L_Pix of the crossing's photons when D_edge < L_Pix / 2 (mode 3: f_c
+// squared). Mode 2 also names the neighbour across that face, which receives the rest
+// (eq:correction2); without one inside the grid the cell keeps everything. Distances in
+// FP64 from the exact boundary numerators; faces within kFaceTie count as tied, and ties go
+// to the lower axis, then the lower face.
+template <int NB>
+__device__ __forceinline__ void geom_correction(const TraceArgs& A, const Ray<NB>& ray, float nhi, float nlo, Seg& sg)
+{
+    sg.nb = kNoCell;
+    sg.fc = 1.0f;
+    if (A.corr == 0) return;
+    const double tm = 0.5 * (((double)ray.thi + (double)ray.tlo) + ((double)nhi + (double)nlo));
+    const int level = (int)(ray.lp >> kLevelShift);
+    const double lpix = tm * __builtin_ldexp(kSqrtPiOver3, -level);
+    double dmin = INFINITY;
+    int axis = 0, side = -1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        // distance to the face the ray heads for (the upper face when d_i = 0)
+        const double ahead = (double)ray.a[i] - tm * (double)ray.e[i];
+        const bool up = ray.step[i] >= 0;
+        const double hi = up ? ahead : 1.0 - ahead;
+        const double lo = up ? 1.0 - ahead : ahead;
+        const bool upper = hi < lo - kFaceTie;
+        const double di = upper ? hi : lo;
+        if (di < dmin - kFaceTie) {
+            dmin = di;
+            axis = i;
+            side = upper ? 1 : -1;
+        }
+    }
+    if (!(dmin < 0.5 * lpix)) return;
+    double fc = 0.5 + dmin / lpix;
+    if (A.corr == 3) fc *= fc;
+    if (A.corr == 2) {
+        const int ca = (axis == 0 ? ray.c[0] : (axis == 1 ? ray.c[1] : ray.c[2])) + side;
+        const int na = axis == 0 ? A.nx : (axis == 1 ? A.ny : A.nz);
+        if (ca < 0 || ca >= na) return;  // no neighbour inside: the cell keeps everything
+        const uint32_t ixa = axis == 0 ? ray.ix[0] : (axis == 1 ? ray.ix[1] : ray.ix[2]);
+        sg.nb = sg.cell - ixa + axis_term(A, axis, ca);
+    }
+    sg.fc = (float)fc;
+}
 
 // Geometry of the next segment (section 2.4: the step to the next x, y or z boundary, or
 // to the split radius), advancing the ray's position and cell.
@@ -289,7 +346,7 @@ struct Seg {
 // 1e-6 is settled exactly with cmp_prod (a_i e_j vs a_j e_i). The winning axis is picked
 // with conditional moves (a runtime index into the per-ray arrays would move them to
 // scratch memory).
-template <int NB, int PREC>
+template <int NB, int PREC, bool CORR = false>
 __device__ __forceinline__ Seg geom_next(const TraceArgs& A, Ray<NB>& ray)
 {
     constexpr float kNear = 1.000001f;
@@ -362,6 +419,7 @@ __device__ __forceinline__ Seg geom_next(const TraceArgs& A, Ray<NB>& ray)
         sg.ds = nhi - ray.thi;
     }
     sg.cell = ray.ix[0] + ray.ix[1] + ray.ix[2];
+    if constexpr (CORR) geom_correction(A, ray, nhi, nlo, sg);
     ray.thi = nhi;
     ray.tlo = nlo;
     if (at_end) {
@@ -438,6 +496,78 @@ __device__ __forceinline__ int deposit_seg(const TraceArgs& A, Ray<NB>& ray, con
     return kContinue;
 }
 
+// deposit_seg with the geometric correction: the crossing's photons (the termination
+// remainder included) are split between its cell (share fc) and, in mode 2, the neighbour
+// sg.nb, where the same photons are absorbed at the neighbour's opacity (times
+// kappa / kappa_nb, eq:correction2 per bin). A neighbour with less than 1/16 of the cell's
+// opacity in a bin takes nothing (the cell keeps that share), which bounds the fixed-point
+// field. Modes 1 and 3 drop the removed share.
+template <int NB, int PREC>
+__device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
+                                                const float kapn[NB], LaneStats& st, Dep<NB>& dep, Dep<NB>& dn)
+{
+    dep.cell = sg.cell;
+    dn.cell = sg.nb;
+    float v[NB];
+    bool term = A.tau_term < INFINITY;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const float dtau = kap[b] * sg.ds;
+        const float taun = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+        v[b] = ((ray.w[b] * transmission(taun)) * sg.ds) * mean_atten(dtau);
+        if constexpr (PREC == 0) {
+            const float s = ray.tau[b] + dtau;
+            const float bb = s - ray.tau[b];
+            ray.taulo[b] += (ray.tau[b] - (s - bb)) + (dtau - bb);
+            ray.tau[b] = s;
+        } else {
+            ray.tau[b] += dtau;
+        }
+        const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+        term = term && taup >= A.tau_term && dtau >= kDtauTermMin;
+    }
+    st.crossings++;
+    if (term) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+            v[b] += (ray.w[b] * transmission(taup)) / kap[b];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        float keep = v[b], move = 0.0f;
+        if (sg.fc < 1.0f) {
+            if (sg.nb == kNoCell) {
+                keep = sg.fc * v[b];
+            } else if (kapn[b] > 0.0f && kap[b] <= 16.0f * kapn[b]) {
+                keep = sg.fc * v[b];
+                move = ((1.0f - sg.fc) * v[b]) * (kap[b] / kapn[b]);
+            }
+        }
+        dep.q[b] = round_to_i64(keep);
+        dn.q[b] = round_to_i64(move);
+    }
+    if (term) {
+        st.terminated++;
+        return kTerminate;
+    }
+    if (sg.event == kSplit) {
+        st.splits++;
+        return kSplit;
+    }
+    if (sg.event == kEscape) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+            st.esc[b] += (double)ray.w[b] * (double)transmission(taup);
+        }
+        st.escaped++;
+        return kEscape;
+    }
+    return kContinue;
+}
+
 // Segments whose geometry is computed ahead of their deposits (opacity loads in flight
 // per lane).
 #ifndef ARC_SEG_AHEAD
@@ -483,6 +613,53 @@ __device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool
             dep[w].cell = kNoCell;
             if (j < K && have[j] && ev == kContinue) ev = deposit_seg<NB, PREC>(A, ray, sg[j], kap[j], st, dep[w]);
         }
+        deposit.add(dep);
+    }
+    deposit.flush();
+    return ev;
+}
+
+// trace_pass with the geometric correction: up to K crossings per lane, the neighbours'
+// opacities loaded with the cells'; each crossing deposits into its cell and its neighbour,
+// which go to the wave's deposit as one window of two items.
+#ifndef ARC_SEG_AHEAD_CORR
+#define ARC_SEG_AHEAD_CORR 4
+#endif
+constexpr int kSegAheadCorr = ARC_SEG_AHEAD_CORR;
+template <int NB, int PREC, int K, class Depositor>
+__device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray, bool active, LaneStats& st,
+                                               Depositor& deposit)
+{
+    static_assert(kDepWindow == 2, "a corrected crossing deposits into two cells");
+    Seg sg[K];
+    bool have[K];
+    bool go = active;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        have[j] = go;
+        if (go) {
+            sg[j] = geom_next<NB, PREC, true>(A, ray);
+            go = sg[j].event == kContinue;
+        }
+    }
+    float kap[K][NB], kapn[K][NB];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) kapn[j][b] = 0.0f;
+        if (have[j]) {
+            kappa_at<NB>(A, sg[j].cell, kap[j]);
+            if (sg[j].nb != kNoCell) kappa_at<NB>(A, sg[j].nb, kapn[j]);
+        }
+    }
+    int ev = kContinue;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        Dep<NB> dep[kDepWindow];
+        dep[0].cell = kNoCell;
+        dep[1].cell = kNoCell;
+        if (have[j] && ev == kContinue)
+            ev = deposit_seg_corr<NB, PREC>(A, ray, sg[j], kap[j], kapn[j], st, dep[0], dep[1]);
         deposit.add(dep);
     }
     deposit.flush();

@@ -326,7 +326,7 @@ hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, cons
 // terminates or leaves the grid; splitting lanes write their four children into the
 // next level's array, one slot reservation per wave.
 // -------------------------------------------------------------------------------------
-template <int NB, int PREC>
+template <int NB, int PREC, bool CORR>
 __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* __restrict__ in,
                                                     const uint32_t* n_in_dev, uint32_t n_in_host,
                                                     RayRec* __restrict__ out, uint32_t* n_out, uint32_t out_cap)
@@ -351,7 +351,11 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
         }
         // a few crossings per lane per pass; the wave deposits each crossing together
         while (__any(act)) {
-            const int e = trace_pass<NB, PREC, kSegAhead>(A, ray, act, st, dep);
+            int e;
+            if constexpr (CORR)
+                e = trace_pass_corr<NB, PREC, kSegAheadCorr>(A, ray, act, st, dep);
+            else
+                e = trace_pass<NB, PREC, kSegAhead>(A, ray, act, st, dep);
             if (act && e != kContinue) {
                 ev = e;
                 act = false;
@@ -382,10 +386,12 @@ static hipError_t trace_rays_nb(const TraceArgs& A, int prec, const RayRec* in, 
                                 uint32_t n_in, RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s)
 {
     const unsigned g = grid_for(n_in, 256, 1u << 16);
-    if (prec == 0)
-        k_trace_rays<NB, 0><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+    if (prec == 0 && A.corr)
+        k_trace_rays<NB, 0, true><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+    else if (prec == 0)
+        k_trace_rays<NB, 0, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
     else
-        k_trace_rays<NB, 1><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+        k_trace_rays<NB, 1, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
     return hipGetLastError();
 }
 
@@ -415,7 +421,7 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 // -------------------------------------------------------------------------------------
 constexpr int kStackCap = 256;  // power of two, >= 3 * 64 children of one split round
 
-template <int NB, int PREC, int WPB>
+template <int NB, int PREC, int WPB, bool CORR>
 __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
                                                                const uint32_t* n_items_dev, uint32_t* head,
                                                                RayRec* __restrict__ spill_all, uint32_t spill_cap,
@@ -498,7 +504,11 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
             if (top == 0 && nspill == 0 && qdone) break;
             continue;
         }
-        const int ev = trace_pass<NB, PREC, kSegAhead>(A, ray, has, st, dep);
+        int ev;
+        if constexpr (CORR)
+            ev = trace_pass_corr<NB, PREC, kSegAheadCorr>(A, ray, has, st, dep);
+        else
+            ev = trace_pass<NB, PREC, kSegAhead>(A, ray, has, st, dep);
         const uint64_t sp = __ballot(ev == kSplit);
         if (sp) {
             const int need = 3 * __popcll(sp);
@@ -541,15 +551,15 @@ constexpr int kMaxWavesPerBlock = 8;
 
 int persistent_max_waves() { return kMaxWavesPerBlock; }
 
-template <int NB, int PREC>
+template <int NB, int PREC, bool CORR>
 static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const uint32_t* n_items, uint32_t* head,
                                 RayRec* spill, uint32_t spill_cap, int blocks, int waves, int refill, hipStream_t s)
 {
     switch (waves) {
-        case 1: k_trace_persistent<NB, PREC, 1><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        case 2: k_trace_persistent<NB, PREC, 2><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        case 4: k_trace_persistent<NB, PREC, 4><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        default: k_trace_persistent<NB, PREC, 8><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 1: k_trace_persistent<NB, PREC, 1, CORR><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 2: k_trace_persistent<NB, PREC, 2, CORR><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 4: k_trace_persistent<NB, PREC, 4, CORR><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        default: k_trace_persistent<NB, PREC, 8, CORR><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
     }
     return hipGetLastError();
 }
@@ -559,8 +569,11 @@ hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* i
                                    int refill, hipStream_t s)
 {
 #define ARC_PERSIST(NBV)                                                                                     \
-    return prec == 0 ? persistent_nb<NBV, 0>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s) \
-                     : persistent_nb<NBV, 1>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s)
+    return prec == 0 ? (A.corr ? persistent_nb<NBV, 0, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, \
+                                                           refill, s)                                            \
+                               : persistent_nb<NBV, 0, false>(A, items, n_items, head, spill, spill_cap, blocks,   \
+                                                            waves, refill, s))                                   \
+                     : persistent_nb<NBV, 1, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s)
     switch (A.nb) {
         case 1: ARC_PERSIST(1);
         case 2: ARC_PERSIST(2);

@@ -1,0 +1,104 @@
+"""GPU parity of the geometric correction (section 2.5, eq:correction, eq:correction2)
+against the oracle: per-cell rates within the parity bar for the three modes and both
+schedules, photon conservation with the secondary deposit (and the same photon deficit as
+the oracle without it), plain and batched schedules bitwise equal, symmetric geometries
+(a source on a grid vertex, where faces tie), a sharp ionisation front, and the
+precision the correction needs."""
+import numpy as np
+import pytest
+
+from helpers import CONSERVATION_TOL, GAMMA_REL_TOL, conservation, rate_errors, run_gpu_trace, run_oracle
+from paper_1807_07094_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"fc": 1, "conserving": 2, "fc_squared": 3}
+
+
+@pytest.fixture(scope="module")
+def ctx(arc):
+    c = arc.Context(0)
+    yield c
+    c.close()
+
+
+def small_lognormal(shape=(40, 48, 56), n_src=4, seed=21):
+    return W.lognormal(0, n_src, seed, source_cells="uniform", shape=shape)
+
+
+def oracle_with(w, mode, **kw):
+    w.trace["correction"] = MODES[mode]
+    try:
+        return run_oracle(w, **kw)
+    finally:
+        w.trace.pop("correction")
+
+
+@pytest.mark.parametrize("schedule", ["plain", "batched"])
+@pytest.mark.parametrize("mode", list(MODES))
+def test_correction_parity(arc, ctx, mode, schedule):
+    w = small_lognormal()
+    print(f"[correction] {mode} {schedule} {w.shape}", flush=True)
+    g = run_gpu_trace(arc, ctx, w, schedule=schedule, correction=mode)
+    o = oracle_with(w, mode)
+    errs = rate_errors(g, o)
+    assert max(errs) <= GAMMA_REL_TOL, errs
+    assert max(rate_errors(g, o, "heat")) <= GAMMA_REL_TOL
+    assert abs(g["ledger"]["crossings"] - o["ledger"]["crossings"]) <= 1e-5 * o["ledger"]["crossings"] + 50
+
+
+def test_conserving_correction_conserves_photons(arc, ctx):
+    w = small_lognormal(seed=7)
+    g2 = run_gpu_trace(arc, ctx, w, correction="conserving")
+    assert conservation(g2["ledger"]) <= CONSERVATION_TOL
+    # without the secondary deposit photons are lost, as many as in the oracle
+    g1 = run_gpu_trace(arc, ctx, w, correction="fc")
+    o1 = oracle_with(w, "fc")
+    gpu_deficit = 1 - g1["ledger"]["absorbed"] / (g1["ledger"]["emitted"] - g1["ledger"]["escaped"])
+    ora_deficit = 1 - o1["absorbed"] / o1["ledger"]["absorbed_trace"]
+    assert ora_deficit > 1e-3
+    assert gpu_deficit == pytest.approx(ora_deficit, rel=1e-4)
+
+
+def test_correction_plain_equals_batched_bitwise(arc, ctx):
+    w = small_lognormal(seed=33)
+    a = run_gpu_trace(arc, ctx, w, schedule="plain", correction="conserving")
+    b = run_gpu_trace(arc, ctx, w, schedule="batched", correction="conserving")
+    c = run_gpu_trace(arc, ctx, w, schedule="batched", correction="conserving", tune_waves=2, tune_refill=1,
+                      tune_blocks=37)
+    assert np.array_equal(a["J"], b["J"])
+    assert np.array_equal(b["J"], c["J"])
+    # and the correction does change the field
+    n = run_gpu_trace(arc, ctx, w, schedule="batched")
+    assert not np.array_equal(n["J"], b["J"])
+
+
+@pytest.mark.parametrize("center", [(16.0, 16.0, 16.0), (16.5, 16.5, 16.5), (31.75, 0.5, 15.0)])
+def test_correction_symmetric_sources(arc, ctx, center):
+    """A source on a grid vertex or a cell centre: many crossings have two faces at the
+    same distance, which both sides settle the same way."""
+    w = W.c1(n=32, center=center, eps_term=1e-6)
+    g = run_gpu_trace(arc, ctx, w, correction="conserving")
+    o = oracle_with(w, "conserving")
+    assert g["ledger"]["crossings"] == o["ledger"]["crossings"]
+    assert rate_errors(g, o)[0] <= GAMMA_REL_TOL
+    assert conservation(g["ledger"]) <= CONSERVATION_TOL
+
+
+def test_correction_across_a_sharp_front(arc, ctx):
+    w = small_lognormal(shape=(32, 30, 28), n_src=3, seed=9)
+    w.grid["x_hi"] = w.grid["x_hi"].copy()
+    w.grid["x_hi"][:, :, 14:] = 1e-4
+    g = run_gpu_trace(arc, ctx, w, correction="conserving")
+    o = oracle_with(w, "conserving")
+    assert max(rate_errors(g, o)) <= GAMMA_REL_TOL
+    assert conservation(g["ledger"]) <= CONSERVATION_TOL
+
+
+def test_correction_needs_compensated_precision(arc, ctx):
+    w = small_lognormal(shape=(8, 8, 8), n_src=1)
+    with pytest.raises(arc.ArcError) as e:
+        run_gpu_trace(arc, ctx, w, precision="fp32_plain", correction="conserving")
+    assert e.value.status == -7
+    with pytest.raises(arc.ArcError):
+        run_gpu_trace(arc, ctx, w, correction=5)

@@ -109,11 +109,11 @@ def hand_field(shape, xs, kappa, S, mode):
             cc = (cx, cy, cz)
             tm = t + 0.5 * s
             best = None
-            for i in range(3):
+            for i in range(3):  # faces within 1e-9 cell are tied: lower axis, then lower face
                 m = xs[i] + tm * d[i]
                 lo, hi = m - cc[i], cc[i] + 1 - m
-                di, side = (lo, -1) if lo <= hi else (hi, 1)
-                if best is None or di < best[0]:
+                di, side = (hi, 1) if hi < lo - 1e-9 else (lo, -1)
+                if best is None or di < best[0] - 1e-9:
                     best = (di, i, side)
             dmin, axis, side = best
             lp = tm * lpix_per_r
