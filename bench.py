@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "bytes_per_crossing": 21.89,
     "sha256": {
-        "paper_1807_07094_amd/csrc/arc_device.h": "804067ef347837df1e09c7fe5a3826d31d4a474d855b69f9803f03f5d8f81e7b",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "cba9ed26fd5e95d5de4d4a393ce8bc5cab199e7bd830bd9c12f16e45c26d20b2",
+        "paper_1807_07094_amd/csrc/arc_device.h": "8b8ac7e153dc653b8aa49bfc0cb1a68ddb7eab45e8e15489439efb3c5b6d7ffc",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "46699469772a00ba8d4ee8ea8a2b5dadec2904f7f5afdb5d9567e7848ad42e9f",
     },
     "profile": "profiles/hbm_traffic_grf1024_16384src.md",
 }
@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--gate-tol", type=float, default=1e-3, help="gate: largest held-out error of a bin")
     ap.add_argument("--cpu-sample", type=int, default=16, help="sources in the oracle's timed sample (0 = skip)")
     ap.add_argument("--plain-sample", type=int, default=256, help="sources traced by the plain schedule (0 = skip)")
+    ap.add_argument("--correction-run", type=int, default=1,
+                    help="1: also trace the workload once with the conserving geometric correction (extra)")
     ap.add_argument("--tune-waves", type=int, default=0)
     ap.add_argument("--tune-blocks", type=int, default=0)
     ap.add_argument("--tune-refill", type=int, default=0)
@@ -241,6 +243,18 @@ def main():
                                  "batched_crossings_per_s": round(lb["crossings"] / tb, 1),
                                  "batched_over_plain": round(tp / tb, 2), "same_crossings": lp["crossings"] == lb["crossings"]}
         log(f"plain sample: {extra['plain_sample']}")
+
+    # The geometric correction (section 2.5, f_c with the conserving secondary deposit) on
+    # the whole workload: one untimed and one timed trace, next to the uncorrected kernel.
+    if args.correction_run and args.schedule == "batched" and args.precision == "fp32_comp":
+        trace(g, w.sources, schedule, correction="conserving", **tune)
+        lc = trace(g, w.sources, schedule, correction="conserving", **tune)
+        extra["correction"] = {"mode": "conserving", "kernel_ms": round(lc["ms_kernel"], 1),
+                               "trace_ms": round(lc["ms_total"], 1), "crossings": lc["crossings"],
+                               "kernel_crossings_per_s": round(lc["crossings"] / (lc["ms_kernel"] * 1e-3), 1),
+                               "over_uncorrected_kernel": round(lc["ms_kernel"] / kms, 3),
+                               "conservation": abs(lc["emitted"] - lc["absorbed"] - lc["escaped"]) / lc["emitted"]}
+        log(f"geometric correction: {extra['correction']}")
 
     cpu = None
     if args.cpu_sample:
