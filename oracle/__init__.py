@@ -94,6 +94,9 @@ def lib():
             [C.c_void_p] * 6
         L.orc_rate_coeffs.restype = None
         L.orc_rate_coeffs.argtypes = [C.c_double, C.c_void_p]
+        L.orc_timestep.restype = None
+        L.orc_timestep.argtypes = [C.c_int64, C.c_double, C.c_double] + [C.c_void_p] * 6 + \
+            [C.POINTER(ChemParams), C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -206,6 +209,12 @@ def finalize(grid: dict, bins: dict, J: np.ndarray):
     return gamma, heat, absorbed.value
 
 
+def _chem_params(cp: dict):
+    return ChemParams(int(cp.get("isothermal", 0)), int(cp.get("rates", 1)), int(cp.get("collisional", 1)),
+                      float(cp.get("alpha_hii", 2.59e-13)), float(cp.get("eps", 0.1)),
+                      int(cp.get("max_sub", 100000)), float(cp.get("t_floor", 1.0)))
+
+
 def chem(grid: dict, state: dict, gamma, heat, dt: float, cp: dict):
     """Chemistry step. state has x_hi, x_hei, x_heii, temp (float32 arrays).
     Returns dict of float64 outputs plus nsub and flags."""
@@ -217,9 +226,7 @@ def chem(grid: dict, state: dict, gamma, heat, dt: float, cp: dict):
     outs = [np.empty(n_h.shape, np.float64) for _ in range(4)]
     nsub = np.empty(n_h.shape, np.int32)
     flags = np.empty(n_h.shape, np.int32)
-    p = ChemParams(int(cp.get("isothermal", 0)), int(cp.get("rates", 1)), int(cp.get("collisional", 1)),
-                   float(cp.get("alpha_hii", 2.59e-13)), float(cp.get("eps", 0.1)),
-                   int(cp.get("max_sub", 100000)), float(cp.get("t_floor", 1.0)))
+    p = _chem_params(cp)
     lib().orc_chem(n, float(grid["y_he"]), _p(n_h), *[_p(x) for x in xs], _p(gamma), _p(heat), float(dt),
                    C.byref(p), *[_p(o) for o in outs], _p(nsub), _p(flags))
     return {"x_hi": outs[0], "x_hei": outs[1], "x_heii": outs[2], "temp": outs[3], "nsub": nsub,
@@ -230,3 +237,20 @@ def rate_coeffs(T: float) -> np.ndarray:
     out = np.empty(6, np.float64)
     lib().orc_rate_coeffs(float(T), _p(out))
     return out
+
+
+def timestep(grid: dict, state: dict, gamma, cp: dict, sigma0: float, eps: float):
+    """Section 2.9 adaptive RT time step: returns (dt_n, dt_I) in seconds. gamma: [3, ...]
+    or [...] photoionisation rates (the HI one is used)."""
+    keep = []
+    n_h = _f32(grid["n_h"])
+    x_hi, x_hei, x_heii, temp = (_f32(state[k]) for k in ("x_hi", "x_hei", "x_heii", "temp"))
+    g = np.ascontiguousarray(gamma, np.float64)
+    ghi = np.ascontiguousarray(g.reshape(-1)[: n_h.size])
+    keep += [n_h, x_hi, x_hei, x_heii, temp, ghi]
+    p = _chem_params(cp)
+    dn, di = C.c_double(0), C.c_double(0)
+    lib().orc_timestep(n_h.size, float(grid["y_he"]), float(grid["cell_cm"]), _p(n_h), _p(x_hi), _p(x_hei),
+                       _p(x_heii), _p(temp), _p(ghi), C.byref(p), float(sigma0), float(eps), C.byref(dn),
+                       C.byref(di))
+    return dn.value, di.value

@@ -688,3 +688,41 @@ void orc_chem(int64_t ncell, double y_he, const float* n_h, const float* x_hi, c
         if (flags) flags[c] = flag;
     }
 }
+
+/* ------------------------------------------------------------------------------ */
+/* Adaptive RT time step (section 2.9): the two per-cell limits and their minima.   */
+/* ------------------------------------------------------------------------------ */
+void orc_timestep(int64_t ncell, double y_he, double cell_cm, const float* n_h, const float* x_hi,
+                  const float* x_hei, const float* x_heii, const float* temp, const double* gamma_hi,
+                  const orc_chem_params* cp, double sigma0, double eps, double* dt_n, double* dt_i)
+{
+    double mn = INFINITY, mi = INFINITY;
+    for (int64_t c = 0; c < ncell; ++c) {
+        const double nh = n_h[c], nhe = y_he * nh;
+        const double nhi = nh * (double)x_hi[c], nhii = nh - nhi;
+        const double nhei = nhe * (double)x_hei[c], nheii = nhe * (double)x_heii[c];
+        double nheiii = nhe - nhei - nheii;
+        if (nheiii < 0) nheiii = 0;
+        const double ne = nhii + nheii + 2.0 * nheiii;
+        double a_hii, k_hi = 0;
+        if (cp->rates == 0) {
+            a_hii = cp->alpha_hii;
+        } else {
+            double k[6];
+            orc_rate_coeffs((double)temp[c], k);
+            a_hii = k[0];
+            if (cp->collisional) k_hi = k[3];
+        }
+        const double ndot = fabs(a_hii * ne * nhii - (gamma_hi[c] + k_hi * ne) * nhi);
+        if (!(ndot > 0)) continue;
+        const double tau = nhi * sigma0 * cell_cm;
+        if (tau > 0.5) {
+            const double t = eps * nhi / ndot;
+            if (t < mn) mn = t;
+        }
+        const double ti = eps / (sigma0 * cell_cm * ndot);
+        if (ti < mi) mi = ti;
+    }
+    *dt_n = mn;
+    *dt_i = mi;
+}

@@ -119,6 +119,17 @@ void orc_chem(int64_t ncell, double y_he, const float* n_h,
               double* x_hi_out, double* x_hei_out, double* x_heii_out, double* temp_out,
               int32_t* nsub, int32_t* flags);
 
+/* Adaptive RT time step (section 2.9) from the current state and rates. Per cell,
+ * ndot_HI = alpha_HII n_e n_HII - (Gamma_HI + k_HI n_e) n_HI (the chemistry's source term
+ * at the start of a step, with the coefficients of cp); then
+ *   dt_n = eps n_HI / |ndot_HI| over cells with tau = n_HI sigma0 L > 0.5,
+ *   dt_I = eps / (sigma0 L |ndot_HI|) over every cell,
+ * sigma0 being the HI cross section of the softest bin. Cells with ndot_HI = 0 impose
+ * nothing; a minimum over no cell is +inf. */
+void orc_timestep(int64_t ncell, double y_he, double cell_cm, const float* n_h, const float* x_hi,
+                  const float* x_hei, const float* x_heii, const float* temp, const double* gamma_hi,
+                  const orc_chem_params* cp, double sigma0, double eps, double* dt_n, double* dt_i);
+
 /* Rate coefficients at temperature T (Hui & Gnedin 1997 fits), exposed for pinning.
  * out: [0] alpha_HII [1] alpha_HeII (incl. dielectronic) [2] alpha_HeIII
  *      [3] k_HI [4] k_HeI [5] k_HeII (collisional ionisation)   all cm^3/s */
