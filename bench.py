@@ -244,6 +244,16 @@ def main():
                                  "batched_over_plain": round(tp / tb, 2), "same_crossings": lp["crossings"] == lb["crossings"]}
         log(f"plain sample: {extra['plain_sample']}")
 
+    # The adaptive RT time step (section 2.9) on the state and rates the timed steps left.
+    if args.chem != "none":
+        t0 = time.perf_counter()
+        dt_n, dt_i = ctx.rt_timestep(g, gamma, w.bins, eps=0.1, rates=w.chem.get("rates", 1),
+                                     collisional=w.chem.get("collisional", 1),
+                                     alpha_hii=w.chem.get("alpha_hii", 2.59e-13))
+        extra["rt_timestep"] = {"eps": 0.1, "dt_n_myr": dt_n / W.MYR_S, "dt_i_myr": dt_i / W.MYR_S,
+                                "ms": round(1e3 * (time.perf_counter() - t0), 2)}
+        log(f"adaptive time step: {extra['rt_timestep']}")
+
     # The geometric correction (section 2.5, f_c with the conserving secondary deposit) on
     # the whole workload: one untimed and one timed trace, next to the uncorrected kernel.
     if args.correction_run and args.schedule == "batched" and args.precision == "fp32_comp":

@@ -293,6 +293,19 @@ typedef struct {
 arc_status arc_chem_step(arc_ctx* ctx, const arc_grid* grid, const arc_rates* rates, double dt,
                          const arc_chem_params* params, arc_chem_stats* stats);
 
+/* Adaptive RT time step (section 2.9) from the grid's current state and the rates of the
+ * last trace. Per cell, ndot_HI = alpha_HII n_e n_HII - (Gamma_HI + k_HI n_e) n_HI, with the
+ * coefficients `params` selects (rates, collisional, alpha_hii; the rest is ignored):
+ *   *dt_n: min of eps n_HI / |ndot_HI| over cells with tau = n_HI sigma0 L > 0.5 (the
+ *          neutral-fraction limit),
+ *   *dt_i: min of eps / (sigma0 L |ndot_HI|) over all cells (the intensity limit),
+ * with sigma0 = bins->sigma[0] (HI cross section of the softest bin) and L = cell_cm.
+ * Cells with ndot_HI = 0 impose nothing; a minimum over no cell is +inf. eps > 0. Blocks
+ * until both values are on the host (host pointers). */
+arc_status arc_rt_timestep(arc_ctx* ctx, const arc_grid* grid, const arc_rates* rates,
+                           const arc_freq_bins* bins, const arc_chem_params* params, double eps,
+                           double* dt_n, double* dt_i);
+
 #ifdef __cplusplus
 }
 #endif

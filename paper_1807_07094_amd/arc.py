@@ -122,6 +122,10 @@ def lib():
         L.arc_chem_step.restype = C.c_int32
         L.arc_chem_step.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Rates), C.c_double,
                                     C.POINTER(ChemParams), C.POINTER(ChemStats)]
+        L.arc_rt_timestep.restype = C.c_int32
+        L.arc_rt_timestep.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Rates), C.POINTER(Bins),
+                                      C.POINTER(ChemParams), C.c_double, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
         L.arc_mlp_create.restype = C.c_int32
         L.arc_mlp_create.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
         L.arc_mlp_destroy.restype = None
@@ -270,6 +274,28 @@ class Context:
         st = ChemStats()
         self._check(lib().arc_chem_step(self._h, C.byref(g), C.byref(r), float(dt), C.byref(p), C.byref(st)))
         return {k: getattr(st, k) for k, _ in ChemStats._fields_}
+
+    def rt_timestep(self, grid, gamma, bins: dict, eps=0.1, rates=1, collisional=1, alpha_hii=2.59e-13,
+                    stream=None):
+        """arc_rt_timestep (section 2.9): (dt_n, dt_I) in seconds from the grid's state and the
+        photoionisation rates gamma [3, nz, ny, nx] of the last trace."""
+        g = _grid(grid)
+        r = Rates(_ptr(gamma), 0)
+        b, _keep = _bins_struct(bins)
+        p = ChemParams(0, int(rates), int(collisional), float(alpha_hii), 0.1, 1, 1.0, 0, _stream(stream), None,
+                       0.0, 0, 0)
+        dn, di = C.c_double(0), C.c_double(0)
+        self._check(lib().arc_rt_timestep(self._h, C.byref(g), C.byref(r), C.byref(b), C.byref(p), float(eps),
+                                          C.byref(dn), C.byref(di)))
+        return dn.value, di.value
+
+
+def _bins_struct(bins):
+    frac = np.ascontiguousarray(bins["frac"], np.float64)
+    e = np.ascontiguousarray(bins["e_erg"], np.float64)
+    sig = np.ascontiguousarray(bins["sigma"], np.float64).reshape(-1, 3)
+    thr = np.ascontiguousarray(bins["e_thr"], np.float64)
+    return Bins(frac.size, _ptr(frac), _ptr(e), _ptr(sig), _ptr(thr)), (frac, e, sig, thr)
 
 
 class MLP:

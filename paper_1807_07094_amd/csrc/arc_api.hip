@@ -1040,6 +1040,48 @@ arc_status ensure_chem_graphs(arc_ctx* c, const ChemPlan& P)
 
 extern "C" {
 
+arc_status arc_rt_timestep(arc_ctx* c, const arc_grid* g, const arc_rates* r, const arc_freq_bins* b,
+                           const arc_chem_params* p, double eps, double* dt_n, double* dt_i)
+{
+    if (!c) return ARC_E_ARG;
+    c->err.clear();
+    arc_status rc;
+    if ((rc = check_grid(c, g)) != ARC_OK) return rc;
+    if ((rc = check_bins(c, b)) != ARC_OK) return rc;
+    if (!g->temp) return fail(c, ARC_E_ARG, "null temperature");
+    if (!r || !r->gamma) return fail(c, ARC_E_ARG, "null rates");
+    if (!p || !dt_n || !dt_i) return fail(c, ARC_E_ARG, "null params or outputs");
+    if (!(eps > 0) || !std::isfinite(eps)) return fail(c, ARC_E_RANGE, "eps must be finite and > 0");
+    if (p->rates != 0 && p->rates != 1) return fail(c, ARC_E_ARG, "rates must be 0 or 1");
+    if (p->rates == 0 && !(p->alpha_hii >= 0)) return fail(c, ARC_E_RANGE, "alpha_hii must be >= 0");
+    hipStream_t st = (hipStream_t)p->stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    TimestepArgs a{};
+    a.ncell = (uint32_t)((size_t)g->nx * g->ny * g->nz);
+    a.y = g->y_he;
+    a.cell_cm = g->cell_cm;
+    a.sigma0 = b->sigma[0];
+    a.eps = eps;
+    a.n_h = g->n_h;
+    a.x_hi = g->x_hi;
+    a.x_hei = g->x_hei;
+    a.x_heii = g->x_heii;
+    a.temp = g->temp;
+    a.gamma_hi = r->gamma;
+    a.rates = p->rates;
+    a.collisional = p->collisional;
+    a.alpha_hii = p->alpha_hii;
+    a.out = c->sums;
+    HIP_TRY(c, launch_timestep_reset(c->sums, st));
+    HIP_TRY(c, launch_timestep(a, c->cus, st));
+    unsigned long long h[2];
+    HIP_TRY(c, hipMemcpyAsync(h, c->sums, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    std::memcpy(dt_n, &h[0], sizeof(double));
+    std::memcpy(dt_i, &h[1], sizeof(double));
+    return ARC_OK;
+}
+
 arc_status arc_chem_step(arc_ctx* c, const arc_grid* g, const arc_rates* r, double dt, const arc_chem_params* p,
                          arc_chem_stats* stats)
 {

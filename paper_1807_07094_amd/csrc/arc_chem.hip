@@ -2,6 +2,7 @@
 //
 //   k_chem             sub-cycled backward-difference chemistry and energy update, one cell
 //                      per lane, lanes refilled from a chunked global cell counter
+//   k_timestep         the adaptive RT time step's two grid minima (section 2.9)
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -206,6 +207,72 @@ hipError_t launch_chem(const ChemArgs& a, int cus, hipStream_t s)
     const size_t want = ((size_t)a.ncell + 255) / 256;
     const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>(want, (size_t)std::max(1, cus) * 8));
     k_chem<<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------------------
+// Adaptive RT time step (section 2.9). Per cell, from the current state and rates, the
+// source term of the HI equation ndot = alpha_HII n_e n_HII - (Gamma_HI + k_HI n_e) n_HI
+// (FP32 coefficients, FP64 densities, as in the solver); then the neutral-fraction limit
+// eps n_HI / |ndot| over cells with tau = n_HI sigma0 L > 0.5 and the intensity limit
+// eps / (sigma0 L |ndot|) over all cells. Minima over the grid: per wave, then one atomic
+// min per wave on the bit patterns of the non-negative doubles (the order of the updates
+// cannot change the result).
+// -------------------------------------------------------------------------------------
+__global__ void k_timestep_reset(unsigned long long* out)
+{
+    if (threadIdx.x < 2) out[threadIdx.x] = 0x7FF0000000000000ull;  // +inf
+}
+
+hipError_t launch_timestep_reset(unsigned long long* out, hipStream_t s)
+{
+    k_timestep_reset<<<1, 64, 0, s>>>(out);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ double wave_min_f64(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_timestep(TimestepArgs a)
+{
+    double mn = INFINITY, mi = INFINITY;
+    const double sl = a.sigma0 * a.cell_cm;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell; c += gridDim.x * blockDim.x) {
+        const double nh = a.n_h[c], nhe = a.y * nh;
+        const double nhi = nh * (double)a.x_hi[c], nhii = nh - nhi;
+        const double nhei = nhe * (double)a.x_hei[c], nheii = nhe * (double)a.x_heii[c];
+        double nheiii = nhe - nhei - nheii;
+        if (nheiii < 0) nheiii = 0;
+        const double ne = nhii + nheii + 2.0 * nheiii;
+        double a_hii, k_hi = 0.0;
+        if (a.rates == 0) {
+            a_hii = a.alpha_hii;
+        } else {
+            const chem::Coef k = chem::coefficients(a.temp[c]);
+            a_hii = (double)k.a_hii;
+            if (a.collisional) k_hi = (double)k.k_hi;
+        }
+        const double ndot = fabs(a_hii * ne * nhii - ((double)a.gamma_hi[c] + k_hi * ne) * nhi);
+        if (!(ndot > 0.0)) continue;
+        if (nhi * sl > 0.5) mn = fmin(mn, a.eps * nhi / ndot);
+        mi = fmin(mi, a.eps / (sl * ndot));
+    }
+    mn = wave_min_f64(mn);
+    mi = wave_min_f64(mi);
+    if ((threadIdx.x & 63) == 0) {
+        if (mn < INFINITY) atomicMin(&a.out[0], (unsigned long long)__double_as_longlong(mn));
+        if (mi < INFINITY) atomicMin(&a.out[1], (unsigned long long)__double_as_longlong(mi));
+    }
+}
+
+hipError_t launch_timestep(const TimestepArgs& a, int cus, hipStream_t s)
+{
+    const size_t want = ((size_t)a.ncell + 255) / 256;
+    const unsigned blocks = (unsigned)std::max<size_t>(1, std::min<size_t>(want, (size_t)std::max(1, cus) * 8));
+    k_timestep<<<blocks, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

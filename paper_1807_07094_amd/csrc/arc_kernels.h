@@ -77,4 +77,18 @@ hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, int nx
 // cus: compute units of the device (the solver launches resident waves only)
 hipError_t launch_chem(const ChemArgs& a, int cus, hipStream_t s);
 
+// Section 2.9 time-step limits: out[0] = min dt_n, out[1] = min dt_I as the bit patterns of
+// non-negative doubles (+inf when no cell constrains); reset with launch_timestep_reset.
+struct TimestepArgs {
+    uint32_t ncell;
+    double y, cell_cm, sigma0, eps;
+    const float *n_h, *x_hi, *x_hei, *x_heii, *temp;
+    const float* gamma_hi;
+    int rates, collisional;
+    double alpha_hii;
+    unsigned long long* out;
+};
+hipError_t launch_timestep_reset(unsigned long long* out, hipStream_t s);
+hipError_t launch_timestep(const TimestepArgs& a, int cus, hipStream_t s);
+
 }  // namespace arc
