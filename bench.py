@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MEASURED_TRAFFIC = {
     "bytes_per_crossing": 21.89,
     "sha256": {
-        "paper_1807_07094_amd/csrc/arc_device.h": "8b8ac7e153dc653b8aa49bfc0cb1a68ddb7eab45e8e15489439efb3c5b6d7ffc",
+        "paper_1807_07094_amd/csrc/arc_device.h": "a3eba0065b7c861299c1f3032ce8ae155c8ca81f13239c1f348cb854e38a6fc5",
         "paper_1807_07094_amd/csrc/arc_kernels.hip": "46699469772a00ba8d4ee8ea8a2b5dadec2904f7f5afdb5d9567e7848ad42e9f",
     },
     "profile": "profiles/hbm_traffic_grf1024_16384src.md",

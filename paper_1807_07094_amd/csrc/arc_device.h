@@ -329,11 +329,21 @@ __device__ __forceinline__ void geom_correction(const TraceArgs& A, const Ray<NB
     double fc = 0.5 + dmin / lpix;
     if (A.corr == 3) fc *= fc;
     if (A.corr == 2) {
-        const int ca = (axis == 0 ? ray.c[0] : (axis == 1 ? ray.c[1] : ray.c[2])) + side;
-        const int na = axis == 0 ? A.nx : (axis == 1 ? A.ny : A.nz);
-        if (ca < 0 || ca >= na) return;  // no neighbour inside: the cell keeps everything
-        const uint32_t ixa = axis == 0 ? ray.ix[0] : (axis == 1 ? ray.ix[1] : ray.ix[2]);
-        sg.nb = sg.cell - ixa + axis_term(A, axis, ca);
+        // the neighbour's per-axis term replaces the cell's along `axis` (static indices only:
+        // a runtime index into the ray's arrays would move them to scratch memory)
+        bool inside = true;
+        uint32_t nb = sg.cell;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (i == axis) {
+                const int ca = ray.c[i] + side;
+                const int na = i == 0 ? A.nx : (i == 1 ? A.ny : A.nz);
+                inside = ca >= 0 && ca < na;
+                if (inside) nb = nb - ray.ix[i] + axis_term(A, i, ca);
+            }
+        }
+        if (!inside) return;  // no neighbour inside: the cell keeps everything
+        sg.nb = nb;
     }
     sg.fc = (float)fc;
 }
@@ -653,14 +663,30 @@ __device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray,
         }
     }
     int ev = kContinue;
+    if (A.corr == 2) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        Dep<NB> dep[kDepWindow];
-        dep[0].cell = kNoCell;
-        dep[1].cell = kNoCell;
-        if (have[j] && ev == kContinue)
-            ev = deposit_seg_corr<NB, PREC>(A, ray, sg[j], kap[j], kapn[j], st, dep[0], dep[1]);
-        deposit.add(dep);
+        for (int j = 0; j < K; ++j) {
+            Dep<NB> dep[kDepWindow];
+            dep[0].cell = kNoCell;
+            dep[1].cell = kNoCell;
+            if (have[j] && ev == kContinue)
+                ev = deposit_seg_corr<NB, PREC>(A, ray, sg[j], kap[j], kapn[j], st, dep[0], dep[1]);
+            deposit.add(dep);
+        }
+    } else {
+        // no neighbour deposits: two segments' cells per window, as without the correction
+#pragma unroll
+        for (int j = 0; j < K; j += 2) {
+            Dep<NB> dep[kDepWindow];
+            Dep<NB> none;
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                dep[w].cell = kNoCell;
+                if (j + w < K && have[j + w] && ev == kContinue)
+                    ev = deposit_seg_corr<NB, PREC>(A, ray, sg[j + w], kap[j + w], kapn[j + w], st, dep[w], none);
+            }
+            deposit.add(dep);
+        }
     }
     deposit.flush();
     return ev;
