@@ -797,7 +797,7 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     if (p->schedule == ARC_SCHED_BATCHED) {
         const int waves = p->tune_waves > 0 ? p->tune_waves : 4;
         const int blocks = p->tune_blocks > 0 ? p->tune_blocks : std::max(1, c->cus * (16 / std::max(1, waves)));
-        const int refill = p->tune_refill > 0 ? p->tune_refill : 8;
+        const int refill = p->tune_refill > 0 ? p->tune_refill : 32;
         if ((rc = shape_batched(c, P, waves, blocks, refill, p->tune_item_level)) != ARC_OK)
             return rc;
     } else if (p->schedule == ARC_SCHED_BATCHED_TUNED) {
@@ -886,7 +886,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
     arc_tune_result best{};
     best.waves = 4;
     best.waves_per_cu = 16;
-    best.refill = 8;
+    best.refill = 32;
     best.item_delta = kDefaultItemDepth;
     double ms_best;
     if ((rc = time_shape(best, &ms_best)) != ARC_OK) return rc;
@@ -920,7 +920,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
         }
     // (3) refill threshold
     const arc_tune_result base3 = best;
-    for (int rf : {4, 16, 32}) {
+    for (int rf : {8, 16, 48}) {
         if (rf == base3.refill) continue;
         arc_tune_result t = base3;
         t.refill = rf;
