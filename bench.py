@@ -272,8 +272,12 @@ def main():
 
         idx = np.arange(0, nsrc, max(1, nsrc // args.cpu_sample))[: args.cpu_sample]
         sub = w.subset(idx)
-        # the chemistry steps above evolved the device state: give the oracle that state
-        state = dict(w.grid, **{k: g[k].cpu().numpy() for k in ("x_hi", "x_hei", "x_heii")})
+        # the oracle takes the workload as generated (nothing the library computed); the
+        # device grid, evolved by the chemistry steps above, goes back to that state for the
+        # GPU side of the sample
+        state = w.grid
+        for k in ("x_hi", "x_hei", "x_heii", "temp"):
+            g[k].copy_(torch.from_numpy(np.ascontiguousarray(w.grid[k], np.float32)))
         log(f"oracle sample: {idx.size} sources on the full {w.shape} grid")
         tc = time.perf_counter()
         r = oracle.trace(state, sub.sources, w.bins, w.trace)

@@ -194,9 +194,11 @@ def gpu_chem(arc, ctx, w, gamma, heat, state=None):
 @pytest.mark.parametrize("which", ["c1", "lognormal"])
 def test_chemistry_parity(arc, ctx, which):
     w = W.c1() if which == "c1" else small_lognormal(seed=5)
-    tr = run_gpu_trace(arc, ctx, w)
-    gpu, st = gpu_chem(arc, ctx, w, tr["gamma"], tr["heat"])
-    ora = oracle.chem(w.grid, w.state(), tr["gamma"].astype(np.float64), tr["heat"].astype(np.float64), w.dt, w.chem)
+    # the same rates for both solvers: the oracle's own, rounded to the FP32 the library takes
+    o = run_oracle(w)
+    gam, hea = o["gamma"].astype(np.float32), o["heat"].astype(np.float32)
+    gpu, st = gpu_chem(arc, ctx, w, gam, hea)
+    ora = oracle.chem(w.grid, w.state(), gam.astype(np.float64), hea.astype(np.float64), w.dt, w.chem)
     for k in ("x_hi", "x_hei", "x_heii"):
         assert np.abs(gpu[k] - ora[k]).max() <= FRACTION_TOL, k
     assert np.max(np.abs(gpu["temp"] / ora["temp"] - 1)) <= 1e-3
