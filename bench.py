@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # and WRITE_SIZE (x1.0) on this workload, valid for the kernel sources with these digests; with
 # any other sources the figure is stale and the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "bytes_per_crossing": 21.89,
+    "bytes_per_crossing": 21.90,
     "sha256": {
         "paper_1807_07094_amd/csrc/arc_device.h": "a3eba0065b7c861299c1f3032ce8ae155c8ca81f13239c1f348cb854e38a6fc5",
         "paper_1807_07094_amd/csrc/arc_kernels.hip": "46699469772a00ba8d4ee8ea8a2b5dadec2904f7f5afdb5d9567e7848ad42e9f",
