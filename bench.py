@@ -79,8 +79,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the tracer runs on a single MI355X; multi-GPU source sharding "
-              "is not built (see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the tracer runs on a single MI355X; sharding the sources over "
+              "several GPUs (an integer sum of their fields) is not built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

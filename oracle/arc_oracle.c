@@ -19,7 +19,7 @@
  *   - Section 2.7 (eq:diffeq, eq:anninos, sub-cycle step) and section 2.8 for the
  *     chemistry and energy update.
  *
- * Readings of points the paper leaves open (each is also listed in the design notes):
+ * Readings of points the paper leaves open:
  *   - Split radius: a level-l ray subtends 4 pi/(12 4^l) sr and splits once its
  *     cross-section exceeds one cell face over Phi (Phi = rays per cell area, fig. 1 and
  *     the methodology test), i.e. at r = 2^l sqrt(3/(pi Phi)) cells. The base value is
