@@ -94,6 +94,10 @@ def lib():
             [C.c_void_p] * 6
         L.orc_rate_coeffs.restype = None
         L.orc_rate_coeffs.argtypes = [C.c_double, C.c_void_p]
+        L.orc_cooling_coeffs.restype = None
+        L.orc_cooling_coeffs.argtypes = [C.c_double, C.c_void_p]
+        L.orc_cooling.restype = C.c_double
+        L.orc_cooling.argtypes = [C.c_double] * 7 + [C.c_int32]
         L.orc_timestep.restype = None
         L.orc_timestep.argtypes = [C.c_int64, C.c_double, C.c_double] + [C.c_void_p] * 6 + \
             [C.POINTER(ChemParams), C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -237,6 +241,20 @@ def rate_coeffs(T: float) -> np.ndarray:
     out = np.empty(6, np.float64)
     lib().orc_rate_coeffs(float(T), _p(out))
     return out
+
+
+def cooling_coeffs(T: float) -> np.ndarray:
+    """[0] HII [1] HeII [2] HeIII recombination cooling, [3] HeII dielectronic cooling,
+    [4] HI [5] HeII collisional excitation, [6] bremsstrahlung per Z^2 [erg cm^3 s^-1]."""
+    out = np.empty(7, np.float64)
+    lib().orc_cooling_coeffs(float(T), _p(out))
+    return out
+
+
+def cooling(T, ne, nhi, nhii, nhei, nheii, nheiii, collisional=1) -> float:
+    """Cooling rate per volume [erg cm^-3 s^-1]."""
+    return float(lib().orc_cooling(float(T), float(ne), float(nhi), float(nhii), float(nhei), float(nheii),
+                                   float(nheiii), int(collisional)))
 
 
 def timestep(grid: dict, state: dict, gamma, cp: dict, sigma0: float, eps: float):

@@ -567,29 +567,45 @@ void orc_rate_coeffs(double T, double out[6])
     out[5] = 19.95 * pow(T, -1.5) * exp(-lheii / 2.0) * pow(lheii, -1.089) / pow(1.0 + pow(lheii / 0.553, 0.735), 1.275);
 }
 
+/* Cooling coefficients per electron and per ion [erg cm^3 s^-1] (section 2.8; Hui & Gnedin
+ * 1997 fits with lambda = 2 T_i / T):
+ *   [0] HII, [1] HeII, [2] HeIII case-B recombination cooling,
+ *   [3] HeII dielectronic recombination cooling,
+ *   [4] HI, [5] HeII collisional excitation,
+ *   [6] bremsstrahlung per unit Z^2 of the ion (Gaunt factor included).
+ * The HeIII recombination term is the HII fit taken at lambda_HeII times Z = 2: a hydrogenic
+ * ion of charge Z cools as Z^3 times hydrogen at T / Z^2, and the fit carries one explicit
+ * power of T. */
+void orc_cooling_coeffs(double T, double out[7])
+{
+    const double lhi = 2.0 * T_HI_K / T, lhei = 2.0 * T_HEI_K / T, lheii = 2.0 * T_HEII_K / T;
+    out[0] = 3.435e-30 * T * pow(lhi, 1.970) / pow(1.0 + pow(lhi / 2.250, 0.376), 3.720);
+    out[1] = KB_ERG * T * 1.26e-14 * pow(lhei, 0.750);
+    out[2] = 2.0 * 3.435e-30 * T * pow(lheii, 1.970) / pow(1.0 + pow(lheii / 2.250, 0.376), 3.720);
+    const double diel = 1.90e-3 * pow(T, -1.5) * exp(-0.75 * lheii / 2.0) * (1.0 + 0.3 * exp(-0.15 * lheii / 2.0));
+    out[3] = 0.75 * 54.418 * EV_ERG * diel;
+    const double damp = 1.0 + sqrt(T / 1e5);
+    out[4] = 7.5e-19 * exp(-0.75 * lhi / 2.0) / damp;
+    out[5] = 5.54e-17 * pow(T, -0.397) * exp(-0.75 * lheii / 2.0) / damp;
+    const double lt = log10(T);
+    const double gff = 1.1 + 0.34 * exp(-(5.5 - lt) * (5.5 - lt) / 3.0);
+    out[6] = 1.42e-27 * gff * sqrt(T);
+}
+
 /* Cooling rate per volume [erg cm^-3 s^-1]: recombination, collisional ionisation,
  * collisional excitation and bremsstrahlung (section 2.8; Hui & Gnedin 1997). The
  * Hubble-expansion and Compton terms need a cosmology and are not included. */
-static double cooling_rate(double T, double ne, double nhi, double nhii, double nhei, double nheii,
-                           double nheiii, int collisional)
+double orc_cooling(double T, double ne, double nhi, double nhii, double nhei, double nheii, double nheiii,
+                   int collisional)
 {
-    const double lhi = 2.0 * T_HI_K / T, lhei = 2.0 * T_HEI_K / T, lheii = 2.0 * T_HEII_K / T;
-    double k[6];
+    double k[6], c[7];
     orc_rate_coeffs(T, k);
-    const double rec_hii = 3.435e-30 * T * pow(lhi, 1.970) / pow(1.0 + pow(lhi / 2.250, 0.376), 3.720);
-    const double rec_heii = KB_ERG * T * 1.26e-14 * pow(lhei, 0.750);
-    const double rec_heiii = 8.0 * 3.435e-30 * T * pow(lheii, 1.970) / pow(1.0 + pow(lheii / 2.250, 0.376), 3.720);
-    const double diel = 1.90e-3 * pow(T, -1.5) * exp(-0.75 * lheii / 2.0) * (1.0 + 0.3 * exp(-0.15 * lheii / 2.0));
-    const double diel_cool = 0.75 * 54.418 * EV_ERG * diel;
-    double lam = ne * (rec_hii * nhii + rec_heii * nheii + rec_heiii * nheiii + diel_cool * nheii);
+    orc_cooling_coeffs(T, c);
+    double lam = ne * (c[0] * nhii + c[1] * nheii + c[2] * nheiii + c[3] * nheii);
     if (collisional)
         lam += ne * (13.598 * EV_ERG * k[3] * nhi + 24.587 * EV_ERG * k[4] * nhei + 54.418 * EV_ERG * k[5] * nheii);
-    const double damp = 1.0 + sqrt(T / 1e5);
-    lam += ne * nhi * 7.5e-19 * exp(-0.75 * lhi / 2.0) / damp;
-    lam += ne * nheii * 5.54e-17 * pow(T, -0.397) * exp(-0.75 * lheii / 2.0) / damp;
-    const double lt = log10(T);
-    const double gff = 1.1 + 0.34 * exp(-(5.5 - lt) * (5.5 - lt) / 3.0);
-    lam += 1.42e-27 * gff * sqrt(T) * (nhii + nheii + 4.0 * nheiii) * ne;
+    lam += ne * (c[4] * nhi + c[5] * nheii);
+    lam += c[6] * (nhii + nheii + 4.0 * nheiii) * ne;
     return lam;
 }
 
@@ -632,7 +648,7 @@ void orc_chem(int64_t ncell, double y_he, const float* n_h, const float* x_hi, c
             double edot = 0;
             if (!cp->isothermal)
                 edot = nhi * hhi + nhei * hhei + nheii * hheii -
-                       cooling_rate(T, ne, nhi, nhii, nhei, nheii, nheiii, cp->collisional);
+                       orc_cooling(T, ne, nhi, nhii, nhei, nheii, nheiii, cp->collisional);
             /* sub-cycle step: limit the fractional change of E and n_HI to eps */
             double h = dt - t;
             int last = 1;

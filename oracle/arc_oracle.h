@@ -135,6 +135,14 @@ void orc_timestep(int64_t ncell, double y_he, double cell_cm, const float* n_h, 
  *      [3] k_HI [4] k_HeI [5] k_HeII (collisional ionisation)   all cm^3/s */
 void orc_rate_coeffs(double T, double out[6]);
 
+/* Cooling coefficients at temperature T [erg cm^3 s^-1], exposed for pinning:
+ *   [0] HII [1] HeII [2] HeIII recombination cooling, [3] HeII dielectronic cooling,
+ *   [4] HI [5] HeII collisional excitation, [6] bremsstrahlung per Z^2 of the ion. */
+void orc_cooling_coeffs(double T, double out[7]);
+/* Cooling rate per volume [erg cm^-3 s^-1] of a gas with these number densities. */
+double orc_cooling(double T, double ne, double nhi, double nhii, double nhei, double nheii, double nheiii,
+                   int collisional);
+
 #ifdef __cplusplus
 }
 #endif

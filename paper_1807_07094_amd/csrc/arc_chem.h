@@ -89,11 +89,12 @@ __device__ __forceinline__ Coef coefficients(float T) { return coefficients(lamb
 __device__ __forceinline__ double cooling(float T, const Lam& l, const Coef& k, double ne, double nhi, double nhii,
                                           double nhei, double nheii, double nheiii, int collisional)
 {
-    // recombination cooling: 3.435e-30 T lambda^1.970 / (1 + (lambda / 2.250)^0.376)^3.720 (HeIII: 8 times, at
-    // lambda_HeII); HeII: k_B T 1.26e-14 lambda_HeI^0.750
+    // recombination cooling: 3.435e-30 T lambda^1.970 / (1 + (lambda / 2.250)^0.376)^3.720; HeIII is
+    // hydrogenic (Z^3 times hydrogen at T / Z^2, Z = 2), i.e. the same fit at lambda_HeII times 2 (the fit
+    // carries one explicit T); HeII: k_B T 1.26e-14 lambda_HeI^0.750
     const float rec_hii = 3.435e-30f * fexp2(l.lt + 1.970f * l.lhi - log2_den(l.lhi, kL2_2250, 0.376f, 3.720f));
     const float rec_heii = (1.380649e-16f * 1.26e-14f) * fexp2(l.lt + 0.750f * l.lhei);
-    const float rec_heiii = 8.0f * 3.435e-30f * fexp2(l.lt + 1.970f * l.lheii - log2_den(l.lheii, kL2_2250, 0.376f, 3.720f));
+    const float rec_heiii = 2.0f * 3.435e-30f * fexp2(l.lt + 1.970f * l.lheii - log2_den(l.lheii, kL2_2250, 0.376f, 3.720f));
     const double diel_cool = 0.75 * 54.418 * kEV * (double)dielectronic(l);
     double lam = ne * ((double)rec_hii * nhii + (double)rec_heii * nheii + (double)rec_heiii * nheiii + diel_cool * nheii);
     if (collisional)
