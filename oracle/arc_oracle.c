@@ -46,10 +46,11 @@
  *     secondary correction the removed share goes to the neighbour across that face,
  *     scaled by the ratio of the two cells' opacities in the bin (eq:correction2's
  *     absorber ratio, read as a density ratio, per bin), which conserves photons; if
- *     that neighbour is outside the grid or has less than 1/16 of the cell's opacity in
- *     the bin (a bound that keeps the fixed-point field of the GPU library finite; it
- *     also conserves photons), the share stays. Faces within 1e-9 cell of each other
- *     count as tied; ties go to the lower axis, then to the lower face.
+ *     that neighbour is outside the grid, or holds no absorber of the bin (zero
+ *     opacity: the ratio has no value), the share stays. Faces within 1e-9 cell of
+ *     each other count as tied; ties go to the lower axis, then to the lower face (a
+ *     tie rule: the nearest face of a midpoint that lies on a cell's diagonal plane is
+ *     not unique, and symmetric geometries put midpoints exactly there).
  */
 #include "arc_oracle.h"
 
@@ -357,15 +358,17 @@ static void orc_deposit(double* J, const double* kappa, int64_t ncell, int k, in
         J[(int64_t)k * ncell + c] += a;
         return;
     }
+    if (nb < 0) {  /* modes 1 and 3: the removed share is dropped */
+        J[(int64_t)k * ncell + c] += fc * a;
+        return;
+    }
     const double kc = kappa[(int64_t)k * ncell + c];
-    const double kn = nb >= 0 ? kappa[(int64_t)k * ncell + nb] : 0.0;
-    if (nb >= 0 && kc <= 16.0 * kn && kn > 0) {
+    const double kn = kappa[(int64_t)k * ncell + nb];
+    if (kn > 0) {
         J[(int64_t)k * ncell + c] += fc * a;
         J[(int64_t)k * ncell + nb] += (1.0 - fc) * a * (kc / kn);
-    } else if (nb >= 0) {
-        J[(int64_t)k * ncell + c] += a;  /* (almost) no absorber next door: the share stays */
     } else {
-        J[(int64_t)k * ncell + c] += fc * a;
+        J[(int64_t)k * ncell + c] += a;  /* no absorber next door: the share stays */
     }
 }
 

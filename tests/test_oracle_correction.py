@@ -62,8 +62,8 @@ def test_secondary_correction_conserves_photons():
 
 
 def test_secondary_correction_conserves_photons_across_a_sharp_front():
-    """Neutral gas next to gas ionised to 1e-4: the neighbours' opacity ratios span both
-    sides of the 1/16 bound, and photons are conserved either way."""
+    """Neutral gas next to gas ionised to 1e-4: opacity ratios of up to 1e4 between
+    neighbours, and photons are conserved."""
     w = lognormal(shape=(20, 20, 20), n_src=2, seed=9)
     w.grid["x_hi"] = w.grid["x_hi"].copy()
     w.grid["x_hi"][:, :, 10:] = 1e-4
@@ -91,10 +91,13 @@ def test_secondary_correction_moves_but_keeps_the_total_in_uniform_gas():
 
 
 def hand_field(shape, xs, kappa, S, mode):
-    """Field of the 12 level-0 rays of one source (no split, no termination) in gas of
-    uniform opacity kappa per cell, from the cell walk: per segment the midpoint, its
-    nearest cell face, the pixel width r_mid sqrt(4 pi / 12), f_c and the neighbour."""
+    """Field of the 12 level-0 rays of one source (no split, no termination) from the cell
+    walk: per segment the midpoint, its nearest cell face, the pixel width
+    r_mid sqrt(4 pi / 12), f_c and the neighbour, which receives the removed share times
+    the opacity ratio (it absorbs the same photons). kappa: opacity per cell length, a
+    number (uniform gas) or an array of the grid's shape."""
     nz, ny, nx = shape
+    kap = np.broadcast_to(np.asarray(kappa, np.float64), shape).reshape(-1)
     J = np.zeros(nx * ny * nz)
     lpix_per_r = math.sqrt(4 * math.pi / 12)
     for pix in range(12):
@@ -120,32 +123,38 @@ def hand_field(shape, xs, kappa, S, mode):
             fc = 1.0 if mode == 0 or dmin >= 0.5 * lp else 0.5 + dmin / lp
             if mode == 3:
                 fc = fc * fc
-            a = P * s * (-math.expm1(-kappa * s) / (kappa * s))
+            k = kap[c]
+            a = P * s * (-math.expm1(-k * s) / (k * s) if k > 0 else 1.0)
             nb = None
             if mode == 2 and fc < 1.0:
                 n3 = list(cc)
                 n3[axis] += side
                 if 0 <= n3[axis] < (nx, ny, nz)[axis]:
                     nb = n3[0] + nx * (n3[1] + ny * n3[2])
-                else:
+                if nb is None or kap[nb] == 0:  # no neighbour, or none that absorbs: the cell keeps it
+                    nb = None
                     fc = 1.0
             J[c] += fc * a
             if nb is not None:
-                J[nb] += (1 - fc) * a
-            P *= math.exp(-kappa * s)
+                J[nb] += (1 - fc) * a * k / kap[nb]
+            P *= math.exp(-k * s)
             t += s
     return J.reshape(shape)
+
+
+def hydrogen_grid(shape, x_hi, kappa_neutral=0.05, L=3.0e20, sigma=6.3e-18):
+    n_h = np.float32(kappa_neutral / (L * sigma))
+    g = {"n_h": np.full(shape, n_h, np.float32), "x_hi": np.ascontiguousarray(x_hi, np.float32),
+         "x_hei": np.zeros(shape, np.float32), "x_heii": np.zeros(shape, np.float32), "cell_cm": L, "y_he": 0.0}
+    # opacity as the oracle forms it from the stored float32 values
+    kappa = L * float(n_h) * sigma * g["x_hi"].astype(np.float64)
+    return g, W.bins_monochromatic(13.6, sigma), kappa
 
 
 @pytest.mark.parametrize("mode", [1, 2, 3])
 def test_correction_matches_a_hand_computation(mode):
     shape = (18, 16, 20)
-    L, sigma = 3.0e20, 6.3e-18
-    n_h = np.float32(0.05 / (L * sigma))
-    kappa = float(n_h) * L * sigma
-    g = {"n_h": np.full(shape, n_h, np.float32), "x_hi": np.ones(shape, np.float32),
-         "x_hei": np.zeros(shape, np.float32), "x_heii": np.zeros(shape, np.float32), "cell_cm": L, "y_he": 0.0}
-    bins = W.bins_monochromatic(13.6, sigma)
+    g, bins, kappa = hydrogen_grid(shape, np.ones(shape))
     xs = [9.25, 7.5, 8.75]
     S = 2e48
     src = {"pos": np.array([xs]), "ndot": np.array([S])}
@@ -158,6 +167,50 @@ def test_correction_matches_a_hand_computation(mode):
     assert (np.abs(J - J0)[lit] / J0[lit]).max() > 0.01  # the correction acts on these rays
     if mode != 2:
         assert J.sum() < J0.sum()
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_correction_matches_a_hand_computation_across_a_sharp_front(mode):
+    """Gas ionised to x_HI = 1e-4 on one side of a plane, neutral on the other: opacity
+    ratios of 1e4 across the front, where eq:correction2 moves the removed share into a
+    cell that absorbs it 1e4 times more weakly (a field 1e4 times the share there)."""
+    shape = (18, 16, 20)
+    x = np.ones(shape)
+    x[:, :, 10:] = 1e-4
+    x[:, 9:, :4] = 1e-4
+    g, bins, kappa = hydrogen_grid(shape, x, kappa_neutral=0.2)
+    xs = [9.25, 7.5, 8.75]
+    S = 2e48
+    src = {"pos": np.array([xs]), "ndot": np.array([S])}
+    p = {"level0": 0, "rays_per_cell": 4.0, "max_level": 0, "eps_term": 0.0, "correction": mode}
+    r = oracle.trace(g, src, bins, p)
+    J = r["J"][0]
+    ref = hand_field(shape, xs, kappa, S, mode)
+    assert np.abs(J - ref).max() <= 1e-12 * ref.max()
+    if mode == 2:
+        # some shares do cross the front into the transparent side
+        J0 = hand_field(shape, xs, kappa, S, 0)
+        ionised = x < 1e-3
+        assert (J[ionised] > 100 * J0[ionised] + 1e-300).any()
+        _, _, absorbed = oracle.finalize(g, bins, r["J"])
+        assert absorbed == pytest.approx(r["ledger"]["absorbed_trace"], rel=1e-10)
+
+
+def test_secondary_correction_keeps_the_share_beside_a_transparent_neighbour():
+    """A neighbour with no absorber (x_HI = 0) cannot take the removed share: the cell
+    keeps it, and photons are still conserved."""
+    shape = (18, 16, 20)
+    x = np.ones(shape)
+    x[:, :, 10:] = 0.0
+    g, bins, kappa = hydrogen_grid(shape, x, kappa_neutral=0.2)
+    xs = [9.25, 7.5, 8.75]
+    src = {"pos": np.array([xs]), "ndot": np.array([2e48])}
+    p = {"level0": 0, "rays_per_cell": 4.0, "max_level": 0, "eps_term": 0.0, "correction": 2}
+    r = oracle.trace(g, src, bins, p)
+    ref = hand_field(shape, xs, kappa, 2e48, 2)
+    assert np.abs(r["J"][0] - ref).max() <= 1e-12 * ref.max()
+    _, _, absorbed = oracle.finalize(g, bins, r["J"])
+    assert absorbed == pytest.approx(r["ledger"]["absorbed_trace"], rel=1e-10)
 
 
 def test_rejects_correction_with_direct_rates_and_unknown_modes():
