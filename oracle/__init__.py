@@ -41,7 +41,8 @@ class Grid(C.Structure):
 
 
 class Sources(C.Structure):
-    _fields_ = [("n", C.c_int32), ("pos", C.c_void_p), ("ndot", C.c_void_p)]
+    _fields_ = [("n", C.c_int32), ("pos", C.c_void_p), ("ndot", C.c_void_p), ("r_thin", C.c_void_p),
+                ("r_thin_out", C.c_void_p)]
 
 
 class Bins(C.Structure):
@@ -57,7 +58,8 @@ class Params(C.Structure):
 class Ledger(C.Structure):
     _fields_ = [("emitted", C.c_double), ("absorbed_trace", C.c_double), ("escaped", C.c_double),
                 ("crossings", C.c_uint64), ("rays", C.c_uint64), ("splits", C.c_uint64),
-                ("terminated", C.c_uint64), ("escaped_rays", C.c_uint64), ("tree_count", C.c_int64)]
+                ("terminated", C.c_uint64), ("escaped_rays", C.c_uint64), ("tree_count", C.c_int64),
+                ("absorbed_thin", C.c_double)]
 
 
 class ChemParams(C.Structure):
@@ -171,14 +173,21 @@ def _bins(b, keep):
 
 
 def trace(grid: dict, sources: dict, bins: dict, params: dict, tree_cap: int = 0, direct: bool = False):
-    """Run the oracle tracer. Returns dict(J [nb,nz,ny,nx], ledger dict, tree, gdir)."""
+    """Run the oracle tracer. Returns dict(J [nb,nz,ny,nx], ledger dict, tree, gdir, r_thin_out).
+    sources may carry "r_thin" (optically thin radius per source, section 2.6); r_thin_out is
+    each source's R_tau<0.1 measured by this trace."""
     keep = []
     g = _grid(grid, keep)
     b = _bins(bins, keep)
     pos = _f64(sources["pos"]).reshape(-1, 3)
     ndot = _f64(sources["ndot"]).reshape(-1)
-    keep += [pos, ndot]
-    s = Sources(ndot.size, _p(pos), _p(ndot))
+    r_thin = sources.get("r_thin")
+    r_thin = _f64(r_thin).reshape(-1) if r_thin is not None else None
+    if r_thin is not None and r_thin.size != ndot.size:
+        raise ValueError("r_thin needs one radius per source")
+    r_out = np.empty(ndot.size, np.float64)
+    keep += [pos, ndot, r_thin, r_out]
+    s = Sources(ndot.size, _p(pos), _p(ndot), _p(r_thin), _p(r_out))
     p = Params(int(params["level0"]), int(params.get("max_level", -1)), float(params["rays_per_cell"]),
                float(params["eps_term"]), int(params.get("correction", 0)))
     shape = (g.nz, g.ny, g.nx)
@@ -191,7 +200,7 @@ def trace(grid: dict, sources: dict, bins: dict, params: dict, tree_cap: int = 0
     if rc != 0:
         raise RuntimeError("orc_trace failed")
     ledger = {k: getattr(led, k) for k, _ in Ledger._fields_}
-    out = {"J": J, "ledger": ledger, "gdir": gdir}
+    out = {"J": J, "ledger": ledger, "gdir": gdir, "r_thin_out": r_out}
     if tree is not None:
         if led.tree_count > tree_cap:
             raise ValueError("tree_cap too small")

@@ -33,6 +33,16 @@
  *     every bin's dtau_b >= 0.01, the remaining photons are absorbed in that cell, so
  *     emitted = absorbed + escaped stays exact. Photons that leave the box are lost.
  *   - Species split inside a bin in proportion to each species' optical depth.
+ *   - Optically thin approximation (section 2.6, optional): a source's radius R is given
+ *     (from the previous step; 0 turns it off) and rounded to float like the split radii.
+ *     Cells whose centre lies within R get the point-source field S_b / (4 pi r^2) of
+ *     every bin, r being the distance of the cell centre in cells, taken as at least half a
+ *     cell (the point formula diverges in the source's own cell); no absorption inside R.
+ *     Rays start at radius R with zero optical depth, at the level whose split radius lies
+ *     beyond R (rays of lower levels split at once, without crossing a cell). The new
+ *     R_tau<0.1 is the least path length at which any ray's optical depth in the softest
+ *     bin reaches 0.1 (inside the crossing where it does, the depth growing linearly), a
+ *     ray that leaves the box (or starts outside it) below 0.1 counting its length there.
  *   - Tie rules: along an axis with d > 0 a point on a boundary belongs to the upper
  *     cell, with d < 0 to the lower cell, with d = 0 to the upper cell; boundaries
  *     reached at exactly the same t are crossed together.
@@ -401,6 +411,11 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
     const int32_t lmax = p->max_level < 0 ? orc_auto_max_level(nx, ny, nz, p->rays_per_cell) : p->max_level;
     const double tau_term = p->eps_term > 0 ? -log(p->eps_term) : INFINITY;
     const double V = L * L * L;
+    /* softest bin: the lowest photon energy (the first of equal ones) */
+    int ksoft = 0;
+    for (int k = 1; k < nb; ++k)
+        if (b->e_erg[k] < b->e_erg[ksoft]) ksoft = k;
+    const double TAU_THIN = 0.1;
 
     stack_t_ st = {0, 0, 0};
     for (int32_t src = 0; src < s->n; ++src) {
@@ -408,6 +423,39 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
         double S[ORC_MAXB];
         for (int k = 0; k < nb; ++k) S[k] = s->ndot[src] * b->frac[k];
         led->emitted += s->ndot[src];
+
+        /* section 2.6: the optically thin sphere of radius R around the source */
+        double R = 0.0;
+        if (s->r_thin) {
+            R = (double)(float)s->r_thin[src];
+            if (!(R >= 0.0) || !isfinite(R)) goto fail;
+        }
+        if (R > 0.0) {
+            const int64_t lo[3] = {(int64_t)floor(xs[0] - R), (int64_t)floor(xs[1] - R), (int64_t)floor(xs[2] - R)};
+            const int64_t hi[3] = {(int64_t)ceil(xs[0] + R), (int64_t)ceil(xs[1] + R), (int64_t)ceil(xs[2] + R)};
+            for (int64_t cz = lo[2] < 0 ? 0 : lo[2]; cz <= hi[2] && cz < nz; ++cz)
+                for (int64_t cy = lo[1] < 0 ? 0 : lo[1]; cy <= hi[1] && cy < ny; ++cy)
+                    for (int64_t cx = lo[0] < 0 ? 0 : lo[0]; cx <= hi[0] && cx < nx; ++cx) {
+                        const double dx = (double)cx + 0.5 - xs[0], dy = (double)cy + 0.5 - xs[1],
+                                     dz = (double)cz + 0.5 - xs[2];
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        if (!(r2 < R * R)) continue;
+                        const double dil = 1.0 / (4.0 * ORC_PI * (r2 > 0.25 ? r2 : 0.25));
+                        const int64_t c = cx + (int64_t)nx * (cy + (int64_t)ny * cz);
+                        for (int k = 0; k < nb; ++k) {
+                            const double a = S[k] * dil;
+                            J[(int64_t)k * ncell + c] += a;
+                            led->absorbed_thin += a * kappa[(int64_t)k * ncell + c];
+                            if (gdir) {
+                                const double nh = g->n_h[c];
+                                const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
+                                for (int sp = 0; sp < 3; ++sp)
+                                    if (ns_[sp] > 0) gdir[(int64_t)sp * ncell + c] += b->sigma[3 * k + sp] * a / (L * L);
+                            }
+                        }
+                    }
+        }
+        double r_out = INFINITY;
 
         ray_t root;
         memset(&root, 0, sizeof(root));
@@ -426,8 +474,21 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
             double v[3], d[3];
             orc_healpix_vec(r.level, r.pix, v);
             for (int i = 0; i < 3; ++i) d[i] = (double)(float)v[i];
-            const double t0 = r.level == p->level0 ? 0.0 : orc_t_split(p->rays_per_cell, r.level - 1);
+            double t0 = r.level == p->level0 ? 0.0 : orc_t_split(p->rays_per_cell, r.level - 1);
+            if (R > t0) t0 = R;
             const double t_end = r.level < lmax ? orc_t_split(p->rays_per_cell, r.level) : INFINITY;
+            if (t0 >= t_end) {
+                /* starts at or beyond its split radius (inside the thin sphere): split at once */
+                ray_t child;
+                memset(&child, 0, sizeof(child));
+                child.level = r.level + 1;
+                for (int q = 3; q >= 0; --q) {
+                    child.pix = 4 * r.pix + q;
+                    if (push(&st, &child)) goto fail;
+                }
+                led->splits++;
+                continue;
+            }
 
             const double wray = 1.0 / (double)orc_npix(r.level);
             double P[ORC_MAXB], tau[ORC_MAXB], dtau[ORC_MAXB];
@@ -439,6 +500,7 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
             if (!walk_start(&w, xs, d, t0, t_end, nx, ny, nz)) {
                 for (int k = 0; k < nb; ++k) led->escaped += P[k];
                 led->escaped_rays++;
+                if (tau[ksoft] < TAU_THIN && t0 < r_out) r_out = t0;
                 continue;
             }
             for (;;) {
@@ -450,6 +512,14 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
                 int64_t cnb = -1;
                 const double fc = p->correction ? orc_correction(&w, w.t, tn, r.level, p->correction, nx, ny, nz, &cnb)
                                                 : 1.0;
+                if (tau[ksoft] < TAU_THIN) {
+                    /* where the softest bin's depth reaches 0.1 inside this crossing */
+                    const double ks = kappa[(int64_t)ksoft * ncell + c];
+                    if (tau[ksoft] + ks * ds >= TAU_THIN) {
+                        const double rc = w.t + (TAU_THIN - tau[ksoft]) / ks;
+                        if (rc < r_out) r_out = rc;
+                    }
+                }
                 for (int k = 0; k < nb; ++k) {
                     const double kap = kappa[(int64_t)k * ncell + c];
                     dtau[k] = kap * ds;
@@ -506,10 +576,12 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
                 if (!walk_inside(&w, nx, ny, nz)) {
                     for (int k = 0; k < nb; ++k) led->escaped += P[k];
                     led->escaped_rays++;
+                    if (tau[ksoft] < TAU_THIN && tn < r_out) r_out = tn;
                     break;
                 }
             }
         }
+        if (s->r_thin_out) s->r_thin_out[src] = r_out;
     }
     free(st.v);
     free(kappa);

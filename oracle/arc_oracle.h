@@ -37,6 +37,9 @@ typedef struct {
     int32_t n;
     const double* pos;       /* [n][3] cell units */
     const double* ndot;      /* [n] ionising photons per second */
+    const double* r_thin;    /* [n] or NULL: optically thin radius of each source (section 2.6),
+                                cells; used rounded to float. NULL = 0 for every source */
+    double* r_thin_out;      /* [n] or NULL: out: each source's new R_tau<0.1 from this trace */
 } orc_sources;
 
 typedef struct {
@@ -67,6 +70,7 @@ typedef struct {
     uint64_t terminated;     /* rays ended by the attenuation criterion */
     uint64_t escaped_rays;   /* rays that left the box */
     int64_t tree_count;      /* rays recorded (may exceed tree_cap) */
+    double absorbed_thin;    /* photons absorbed by the optically thin fill, sum J_fill kappa [photons/s] */
 } orc_ledger;
 
 /* HEALPix, nested scheme (Gorski et al. 2005, ApJ 622, 759). */
@@ -83,7 +87,14 @@ int32_t orc_auto_max_level(int32_t nx, int32_t ny, int32_t nz, double rays_per_c
 int64_t orc_walk(int32_t nx, int32_t ny, int32_t nz, const double xs[3], const double d[3],
                  double t0, double t_end, int64_t* cells, double* ds, int64_t cap, int32_t* how);
 
-/* One ray-tracing pass over all sources (section 2.1 steps iii a-d, section 2.4).
+/* One ray-tracing pass over all sources (section 2.1 steps iii a-d, section 2.4), with the
+ * optically thin approximation of section 2.6 for sources with r_thin > 0: cells whose centre
+ * lies within R of the source receive S_b / (4 pi r^2) of field (r the centre's distance in
+ * cells, at least 1/2), and the source's rays start at radius R with zero optical depth (a ray
+ * whose level's split radius is not beyond R splits at once, without a crossing). With
+ * r_thin_out, each source's R_tau<0.1 is measured: the least path length at which a ray's
+ * optical depth in the softest bin (lowest energy) reaches 0.1, a path that leaves the box
+ * below 0.1 counting with its length at the box face.
  *   J      [nbins][ncell] out: sum over crossings of P_b * ds * g(dtau_b)   [photons/s * cells]
  *   gdir   [3][ncell] out or NULL: photoionisation rate per absorber summed directly in the
  *          form of eq:ion with the in-bin species split (for checking the J route)

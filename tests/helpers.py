@@ -27,9 +27,14 @@ def run_gpu_trace(arc_mod, ctx, w, schedule="batched", precision="fp32_comp", tr
                     eps_term=w.trace["eps_term"] if eps_term is None else eps_term, precision=precision,
                     schedule=schedule, tree=tree, **kw)
     nb = len(w.bins["frac"])
-    J = torch.empty((nb,) + w.shape, dtype=torch.int64, device="cuda")
+    # with the conserving correction the moved-photon field's two limbs follow the field
+    parts = 3 if kw.get("correction") in ("conserving", 2) else 1
+    J = torch.empty((parts, nb) + w.shape, dtype=torch.int64, device="cuda")
     ctx.get_field(J)
-    out = {"gamma": gamma.cpu().numpy(), "heat": heat.cpu().numpy(), "J": J.cpu().numpy(), "ledger": led}
+    Jh = J.cpu().numpy()
+    out = {"gamma": gamma.cpu().numpy(), "heat": heat.cpu().numpy(), "J": Jh[0], "ledger": led}
+    if parts == 3:
+        out["moved_lo"], out["moved_hi"] = Jh[1], Jh[2]
     if tree is not None:
         n = min(led["tree_count"], tree_cap)
         out["tree"] = np.sort(tree[:n].cpu().numpy().view(np.uint64))

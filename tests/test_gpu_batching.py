@@ -4,12 +4,16 @@
   with other GPU work and synchronisations between the replays, and a change of the
   sources' luminosities (new fixed-point scales) is recorded afresh;
 * the autotuner's chosen shape, and the tuned schedule (tuned on first use), reach the
-  plain schedule's fixed-point field exactly.
+  plain schedule's fixed-point field exactly;
+* rays moved from a wave's on-chip stack to its spill area in memory and back (deep
+  subtrees: work items at the first level) give the plain schedule's field bit for bit
+  and the oracle's rates; a spill area too small for them fails with ARC_E_QUEUE and
+  leaves the context usable.
 """
 import numpy as np
 import pytest
 
-from helpers import run_gpu_trace
+from helpers import CONSERVATION_TOL, GAMMA_REL_TOL, conservation, rate_errors, run_gpu_trace, run_oracle
 from paper_1807_07094_amd import workload as W
 
 pytestmark = pytest.mark.gpu
@@ -109,3 +113,36 @@ def test_chemistry_graph_replays_equal_eager(arc, ctx):
         a = torch.randn(256, 256, device="cuda")
         float((a @ a).sum())
         torch.cuda.synchronize()
+
+
+def deep_subtrees():
+    # level-1 work items on a 96^3 grid: every item is a whole subtree of up to 8 levels,
+    # far more than a wave's 256-record stack holds
+    return W.lognormal(96, 8, 25, source_cells="uniform")
+
+
+def test_spilled_rays_match_plain_and_oracle(arc, ctx):
+    w = deep_subtrees()
+    print(f"[spill] {w.shape} {len(w.sources['ndot'])} sources, item level {w.trace['level0']}", flush=True)
+    b = run_gpu_trace(arc, ctx, w, schedule="batched", tune_item_level=w.trace["level0"], tune_waves=1)
+    assert b["ledger"]["spills"] > 0, b["ledger"]
+    p = run_gpu_trace(arc, ctx, w, schedule="plain")
+    assert np.array_equal(b["J"], p["J"])
+    assert b["ledger"]["crossings"] == p["ledger"]["crossings"]
+    o = run_oracle(w)
+    assert max(rate_errors(b, o)) <= GAMMA_REL_TOL
+    assert conservation(b["ledger"]) <= CONSERVATION_TOL
+
+
+def test_spill_area_overflow_is_reported_and_context_reused(arc, ctx):
+    w = deep_subtrees()
+    with pytest.raises(arc.ArcError) as e:
+        run_gpu_trace(arc, ctx, w, schedule="batched", tune_item_level=w.trace["level0"], tune_waves=1, spill_cap=2)
+    assert e.value.status == -6, e.value
+    # the same context traces correctly afterwards
+    again = run_gpu_trace(arc, ctx, w, schedule="batched", tune_item_level=w.trace["level0"], tune_waves=1)
+    p = run_gpu_trace(arc, ctx, w, schedule="plain")
+    assert np.array_equal(again["J"], p["J"])
+    with pytest.raises(arc.ArcError) as e:
+        run_gpu_trace(arc, ctx, w, schedule="batched", spill_cap=-1)
+    assert e.value.status == -1

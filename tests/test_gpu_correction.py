@@ -2,8 +2,8 @@
 against the oracle: per-cell rates within the parity bar for the three modes and both
 schedules, photon conservation with the secondary deposit (and the same photon deficit as
 the oracle without it), plain and batched schedules bitwise equal, symmetric geometries
-(a source on a grid vertex, where faces tie), a sharp ionisation front, and the
-precision the correction needs."""
+(a source on a grid vertex, where faces tie), sharp ionisation fronts (opacity ratios up
+to 1e5, and neighbours with no absorber), and the precision the correction needs."""
 import numpy as np
 import pytest
 
@@ -66,8 +66,10 @@ def test_correction_plain_equals_batched_bitwise(arc, ctx):
     b = run_gpu_trace(arc, ctx, w, schedule="batched", correction="conserving")
     c = run_gpu_trace(arc, ctx, w, schedule="batched", correction="conserving", tune_waves=2, tune_refill=1,
                       tune_blocks=37)
-    assert np.array_equal(a["J"], b["J"])
-    assert np.array_equal(b["J"], c["J"])
+    for key in ("J", "moved_lo", "moved_hi"):
+        assert np.array_equal(a[key], b[key]), key
+        assert np.array_equal(b[key], c[key]), key
+    assert b["moved_hi"].any() and b["moved_lo"].any()
     # and the correction does change the field
     n = run_gpu_trace(arc, ctx, w, schedule="batched")
     assert not np.array_equal(n["J"], b["J"])
@@ -93,6 +95,26 @@ def test_correction_across_a_sharp_front(arc, ctx):
     o = oracle_with(w, "conserving")
     assert max(rate_errors(g, o)) <= GAMMA_REL_TOL
     assert conservation(g["ledger"]) <= CONSERVATION_TOL
+
+
+def test_correction_into_nearly_transparent_neighbours(arc, ctx):
+    """Hydrogen gas, neutral on one side of a plane and ionised to 1e-5 (or fully, x_HI = 0)
+    on the other: opacity ratios of 1e5 across the front, where eq:correction2 puts a field
+    1e5 times the moved share into the ionised cell; next to x_HI = 0 the cell keeps it."""
+    for x_ion in (1e-5, 0.0):
+        w = W.c1(n=32, center=(12.25, 15.5, 16.75), eps_term=1e-6)
+        w.grid["x_hi"] = w.grid["x_hi"].copy()
+        w.grid["x_hi"][:, :, 14:] = x_ion
+        w.grid["x_hi"][20:, :, :] = x_ion
+        print(f"[correction] front x_ion={x_ion}", flush=True)
+        g = run_gpu_trace(arc, ctx, w, correction="conserving")
+        o = oracle_with(w, "conserving")
+        assert g["ledger"]["crossings"] == o["ledger"]["crossings"]
+        errs = rate_errors(g, o)
+        assert errs[0] <= GAMMA_REL_TOL, errs
+        assert conservation(g["ledger"]) <= CONSERVATION_TOL
+        if x_ion == 0.0:
+            assert not g["moved_hi"][0][w.grid["x_hi"] == 0.0].any()
 
 
 def test_correction_needs_compensated_precision(arc, ctx):

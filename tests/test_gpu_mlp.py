@@ -4,6 +4,9 @@
 * a gate that accepts nothing reproduces the plain solver bitwise;
 * with the gate on, every accepted cell stays within the tolerance of the plain solver
   (the plain solver is the judge; it is itself parity-checked against the oracle);
+* the gated step judged by the FP64 oracle's chemistry directly: from the same state and
+  the same rates (the oracle's own, rounded to FP32), every cell's fractions within 1e-3
+  and temperature within 1e-2 relative, accepted cells and fallback cells alike;
 * save / load round trip.
 """
 import struct
@@ -163,6 +166,32 @@ def test_gated_step_within_tolerance_of_plain(arc, ctx, trained):
     assert float(dt.max()) <= 1e-2
     # helium is untouched by the network and equal to the plain solver where it fell back
     assert float((gated["x_heii"] - plain["x_heii"]).abs().max()) <= 1e-3
+
+
+def test_gated_step_judged_by_the_oracle(arc, ctx, trained):
+    import torch
+
+    import oracle
+
+    net = trained[0]
+    w = W.lognormal(48, 32, 79)
+    # rates from the oracle's trace of the grid as generated, rounded to FP32 for both sides
+    r = oracle.trace(w.grid, w.sources, w.bins, w.trace)
+    og, oh, _ = oracle.finalize(w.grid, w.bins, r["J"])
+    g32, h32 = og.astype(np.float32), oh.astype(np.float32)
+    g = arc.device_grid(w.grid)
+    gamma = torch.from_numpy(g32).cuda()
+    heat = torch.from_numpy(h32).cuda()
+    st = ctx.chem_step(g, gamma, heat, w.dt, mode="mlp_gated", mlp=net, gate_tol=1e-3, **w.chem)
+    accepted = st["cells"] - st["fallback"]
+    print(f"[mlp judge] accepted {accepted} of {st['cells']} cells", flush=True)
+    assert accepted > 0
+    ref = oracle.chem(w.grid, w.state(), g32.astype(np.float64), h32.astype(np.float64), w.dt, w.chem)
+    for k in ("x_hi", "x_hei", "x_heii"):
+        err = float(np.abs(g[k].cpu().numpy() - ref[k]).max())
+        assert err <= 1e-3, (k, err)
+    t_err = float(np.abs(g["temp"].cpu().numpy() / ref["temp"] - 1).max())
+    assert t_err <= 1e-2, t_err
 
 
 def test_save_load_round_trip(arc, ctx, trained):
