@@ -25,8 +25,8 @@ _lib = None
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc into oracle/_build/libarc_oracle.so."""
     os.makedirs(_LIB_DIR, exist_ok=True)
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           "-o", _LIB + ".tmp", _SRC, "-lm"]
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-pthread", "-fno-strict-aliasing", "-Wall", "-Wextra",
+           "-Wno-unused-parameter", "-o", _LIB + ".tmp", _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -88,6 +88,9 @@ def lib():
         L.orc_trace.restype = C.c_int32
         L.orc_trace.argtypes = [C.POINTER(Grid), C.POINTER(Sources), C.POINTER(Bins), C.POINTER(Params),
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Ledger)]
+        L.orc_trace_mt.restype = C.c_int32
+        L.orc_trace_mt.argtypes = [C.POINTER(Grid), C.POINTER(Sources), C.POINTER(Bins), C.POINTER(Params),
+                                   C.c_void_p, C.c_int32, C.POINTER(Ledger)]
         L.orc_finalize.restype = None
         L.orc_finalize.argtypes = [C.POINTER(Grid), C.POINTER(Bins), C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.POINTER(C.c_double)]
@@ -206,6 +209,28 @@ def trace(grid: dict, sources: dict, bins: dict, params: dict, tree_cap: int = 0
             raise ValueError("tree_cap too small")
         out["tree"] = tree[: led.tree_count]
     return out
+
+
+def trace_mt(grid: dict, sources: dict, bins: dict, params: dict, threads: int):
+    """The oracle tracer with the sources split over host threads (one shared field, atomic
+    additions). Returns dict(J, ledger, r_thin_out)."""
+    keep = []
+    g = _grid(grid, keep)
+    b = _bins(bins, keep)
+    pos = _f64(sources["pos"]).reshape(-1, 3)
+    ndot = _f64(sources["ndot"]).reshape(-1)
+    r_thin = sources.get("r_thin")
+    r_thin = _f64(r_thin).reshape(-1) if r_thin is not None else None
+    r_out = np.empty(ndot.size, np.float64)
+    keep += [pos, ndot, r_thin, r_out]
+    s = Sources(ndot.size, _p(pos), _p(ndot), _p(r_thin), _p(r_out))
+    p = Params(int(params["level0"]), int(params.get("max_level", -1)), float(params["rays_per_cell"]),
+               float(params["eps_term"]), int(params.get("correction", 0)))
+    J = np.empty((b.nbins, g.nz, g.ny, g.nx), np.float64)
+    led = Ledger()
+    if lib().orc_trace_mt(C.byref(g), C.byref(s), C.byref(b), C.byref(p), _p(J), int(threads), C.byref(led)) != 0:
+        raise RuntimeError("orc_trace_mt failed")
+    return {"J": J, "ledger": {k: getattr(led, k) for k, _ in Ledger._fields_}, "r_thin_out": r_out}
 
 
 def finalize(grid: dict, bins: dict, J: np.ndarray):

@@ -65,6 +65,7 @@
 #include "arc_oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -358,40 +359,263 @@ static double orc_correction(const walk_t* w, double t0, double t1, int32_t leve
     return fc;
 }
 
+/* What every source's trace shares: inputs, opacity, levels, and whether the field is
+ * shared between threads (then every addition to it is atomic). */
+typedef struct {
+    const orc_grid* g;
+    const orc_sources* s;
+    const orc_bins* b;
+    const orc_params* p;
+    const double* kappa;     /* [nbins][ncell] optical depth per cell length */
+    int64_t ncell;
+    int nb, ksoft;
+    int32_t lmax;
+    double tau_term;
+    int atomic;
+} orc_run;
+
+/* x += v, atomically when the field is shared between threads (compare-and-swap on the
+ * bit pattern: the sum is the same up to the order of the additions). */
+static void field_add(const orc_run* R, double* x, double v)
+{
+    if (!R->atomic) {
+        *x += v;
+        return;
+    }
+    uint64_t* u = (uint64_t*)(void*)x;
+    uint64_t old = __atomic_load_n(u, __ATOMIC_RELAXED), nw;
+    do {
+        double d;
+        memcpy(&d, &old, sizeof d);
+        d += v;
+        memcpy(&nw, &d, sizeof nw);
+    } while (!__atomic_compare_exchange_n(u, &old, nw, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED));
+}
+
 /* Field deposit of amount a (photons per unit opacity) of bin k into cell c, split by the
  * geometric correction: f_c a stays; with a neighbour, (1 - f_c) a kappa_c / kappa_nb goes
  * there (the same photons, absorbed at the neighbour's opacity). */
-static void orc_deposit(double* J, const double* kappa, int64_t ncell, int k, int64_t c, double a, double fc,
-                        int64_t nb)
+static void orc_deposit(const orc_run* R, double* J, int k, int64_t c, double a, double fc, int64_t nb)
 {
+    const int64_t ncell = R->ncell;
     if (fc >= 1.0) {
-        J[(int64_t)k * ncell + c] += a;
+        field_add(R, &J[(int64_t)k * ncell + c], a);
         return;
     }
     if (nb < 0) {  /* modes 1 and 3: the removed share is dropped */
-        J[(int64_t)k * ncell + c] += fc * a;
+        field_add(R, &J[(int64_t)k * ncell + c], fc * a);
         return;
     }
-    const double kc = kappa[(int64_t)k * ncell + c];
-    const double kn = kappa[(int64_t)k * ncell + nb];
+    const double kc = R->kappa[(int64_t)k * ncell + c];
+    const double kn = R->kappa[(int64_t)k * ncell + nb];
     if (kn > 0) {
-        J[(int64_t)k * ncell + c] += fc * a;
-        J[(int64_t)k * ncell + nb] += (1.0 - fc) * a * (kc / kn);
+        field_add(R, &J[(int64_t)k * ncell + c], fc * a);
+        field_add(R, &J[(int64_t)k * ncell + nb], (1.0 - fc) * a * (kc / kn));
     } else {
-        J[(int64_t)k * ncell + c] += a;  /* no absorber next door: the share stays */
+        field_add(R, &J[(int64_t)k * ncell + c], a);  /* no absorber next door: the share stays */
     }
 }
 
-int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, const orc_params* p,
-                  double* J, double* gdir, uint64_t* tree, int64_t tree_cap, orc_ledger* led)
+/* Everything one source contributes (section 2.6 fill, then its ray tree, depth first).
+ * st is the caller's (emptied) stack. Returns 0, or -1 on a bad thin radius or an
+ * allocation failure. */
+static int32_t trace_source(const orc_run* R, int32_t src, double* J, double* gdir, uint64_t* tree,
+                            int64_t tree_cap, orc_ledger* led, stack_t_* st)
+{
+    const orc_grid* g = R->g;
+    const orc_sources* s = R->s;
+    const orc_bins* b = R->b;
+    const orc_params* p = R->p;
+    const double* kappa = R->kappa;
+    const int nb = R->nb, ksoft = R->ksoft;
+    const int32_t nx = g->nx, ny = g->ny, nz = g->nz, lmax = R->lmax;
+    const int64_t ncell = R->ncell;
+    const double L = g->cell_cm, y = g->y_he, V = L * L * L, tau_term = R->tau_term;
+    const double TAU_THIN = 0.1;
+
+    const double* xs = s->pos + 3 * src;
+    double S[ORC_MAXB];
+    for (int k = 0; k < nb; ++k) S[k] = s->ndot[src] * b->frac[k];
+    led->emitted += s->ndot[src];
+
+    /* section 2.6: the optically thin sphere of radius R around the source */
+    double Rt = 0.0;
+    if (s->r_thin) {
+        Rt = (double)(float)s->r_thin[src];
+        if (!(Rt >= 0.0) || !isfinite(Rt)) return -1;
+    }
+    if (Rt > 0.0) {
+        const int64_t lo[3] = {(int64_t)floor(xs[0] - Rt), (int64_t)floor(xs[1] - Rt), (int64_t)floor(xs[2] - Rt)};
+        const int64_t hi[3] = {(int64_t)ceil(xs[0] + Rt), (int64_t)ceil(xs[1] + Rt), (int64_t)ceil(xs[2] + Rt)};
+        for (int64_t cz = lo[2] < 0 ? 0 : lo[2]; cz <= hi[2] && cz < nz; ++cz)
+            for (int64_t cy = lo[1] < 0 ? 0 : lo[1]; cy <= hi[1] && cy < ny; ++cy)
+                for (int64_t cx = lo[0] < 0 ? 0 : lo[0]; cx <= hi[0] && cx < nx; ++cx) {
+                    const double dx = (double)cx + 0.5 - xs[0], dy = (double)cy + 0.5 - xs[1],
+                                 dz = (double)cz + 0.5 - xs[2];
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (!(r2 < Rt * Rt)) continue;
+                    const double dil = 1.0 / (4.0 * ORC_PI * (r2 > 0.25 ? r2 : 0.25));
+                    const int64_t c = cx + (int64_t)nx * (cy + (int64_t)ny * cz);
+                    for (int k = 0; k < nb; ++k) {
+                        const double a = S[k] * dil;
+                        field_add(R, &J[(int64_t)k * ncell + c], a);
+                        led->absorbed_thin += a * kappa[(int64_t)k * ncell + c];
+                        if (gdir) {
+                            const double nh = g->n_h[c];
+                            const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
+                            for (int sp = 0; sp < 3; ++sp)
+                                if (ns_[sp] > 0) gdir[(int64_t)sp * ncell + c] += b->sigma[3 * k + sp] * a / (L * L);
+                        }
+                    }
+                }
+    }
+    double r_out = INFINITY;
+
+    ray_t root;
+    memset(&root, 0, sizeof(root));
+    root.level = p->level0;
+    for (int64_t q = orc_npix(p->level0) - 1; q >= 0; --q) {
+        root.pix = q;
+        if (push(st, &root)) return -1;
+    }
+    while (st->n > 0) {
+        const ray_t r = st->v[--st->n];
+        if (tree && led->tree_count < tree_cap)
+            tree[led->tree_count] = ((uint64_t)src << 32) | ((uint64_t)r.level << 28) | (uint64_t)r.pix;
+        led->tree_count++;
+        led->rays++;
+
+        double v[3], d[3];
+        orc_healpix_vec(r.level, r.pix, v);
+        for (int i = 0; i < 3; ++i) d[i] = (double)(float)v[i];
+        double t0 = r.level == p->level0 ? 0.0 : orc_t_split(p->rays_per_cell, r.level - 1);
+        if (Rt > t0) t0 = Rt;
+        const double t_end = r.level < lmax ? orc_t_split(p->rays_per_cell, r.level) : INFINITY;
+        if (t0 >= t_end) {
+            /* starts at or beyond its split radius (inside the thin sphere): split at once */
+            ray_t child;
+            memset(&child, 0, sizeof(child));
+            child.level = r.level + 1;
+            for (int q = 3; q >= 0; --q) {
+                child.pix = 4 * r.pix + q;
+                if (push(st, &child)) return -1;
+            }
+            led->splits++;
+            continue;
+        }
+
+        const double wray = 1.0 / (double)orc_npix(r.level);
+        double P[ORC_MAXB], tau[ORC_MAXB], dtau[ORC_MAXB];
+        for (int k = 0; k < nb; ++k) {
+            tau[k] = r.tau[k];
+            P[k] = S[k] * wray * exp(-tau[k]);
+        }
+        walk_t w;
+        if (!walk_start(&w, xs, d, t0, t_end, nx, ny, nz)) {
+            for (int k = 0; k < nb; ++k) led->escaped += P[k];
+            led->escaped_rays++;
+            if (tau[ksoft] < TAU_THIN && t0 < r_out) r_out = t0;
+            continue;
+        }
+        for (;;) {
+            int at_end, mask;
+            const double tn = walk_next(&w, &at_end, &mask);
+            const double ds = tn - w.t;
+            const int64_t c = w.c[0] + (int64_t)nx * (w.c[1] + (int64_t)ny * w.c[2]);
+            led->crossings++;
+            int64_t cnb = -1;
+            const double fc = p->correction ? orc_correction(&w, w.t, tn, r.level, p->correction, nx, ny, nz, &cnb)
+                                            : 1.0;
+            if (tau[ksoft] < TAU_THIN) {
+                /* where the softest bin's depth reaches 0.1 inside this crossing */
+                const double ks = kappa[(int64_t)ksoft * ncell + c];
+                if (tau[ksoft] + ks * ds >= TAU_THIN) {
+                    const double rc = w.t + (TAU_THIN - tau[ksoft]) / ks;
+                    if (rc < r_out) r_out = rc;
+                }
+            }
+            for (int k = 0; k < nb; ++k) {
+                const double kap = kappa[(int64_t)k * ncell + c];
+                dtau[k] = kap * ds;
+                const double lost = -expm1(-dtau[k]);        /* 1 - e^-dtau */
+                orc_deposit(R, J, k, c, P[k] * ds * mean_atten(dtau[k]), fc, cnb);
+                led->absorbed_trace += P[k] * lost;
+                if (gdir && dtau[k] > 0) {
+                    /* eq:ion with the absorbed photons split by species optical depth */
+                    const double nh = g->n_h[c];
+                    const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
+                    for (int sp = 0; sp < 3; ++sp) {
+                        if (ns_[sp] <= 0) continue;
+                        const double dts = L * ns_[sp] * b->sigma[3 * k + sp] * ds;
+                        gdir[(int64_t)sp * ncell + c] += P[k] * lost * (dts / dtau[k]) / (V * ns_[sp]);
+                    }
+                }
+                P[k] *= exp(-dtau[k]);
+                tau[k] += dtau[k];
+            }
+            int term = tau_term < INFINITY;
+            for (int k = 0; k < nb && term; ++k)
+                term = tau[k] >= tau_term && dtau[k] >= ORC_DTAU_TERM_MIN;
+            if (term) {
+                for (int k = 0; k < nb; ++k) {
+                    const double kap = kappa[(int64_t)k * ncell + c];
+                    orc_deposit(R, J, k, c, P[k] / kap, fc, cnb);
+                    led->absorbed_trace += P[k];
+                    if (gdir) {
+                        const double nh = g->n_h[c];
+                        const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
+                        for (int sp = 0; sp < 3; ++sp) {
+                            if (ns_[sp] <= 0) continue;
+                            const double ks = L * ns_[sp] * b->sigma[3 * k + sp];
+                            gdir[(int64_t)sp * ncell + c] += P[k] * (ks / kap) / (V * ns_[sp]);
+                        }
+                    }
+                }
+                led->terminated++;
+                break;
+            }
+            if (at_end) {
+                ray_t child;
+                memset(&child, 0, sizeof(child));
+                child.level = r.level + 1;
+                for (int k = 0; k < nb; ++k) child.tau[k] = tau[k];
+                for (int q = 3; q >= 0; --q) {
+                    child.pix = 4 * r.pix + q;
+                    if (push(st, &child)) return -1;
+                }
+                led->splits++;
+                break;
+            }
+            walk_advance(&w, mask, tn);
+            if (!walk_inside(&w, nx, ny, nz)) {
+                for (int k = 0; k < nb; ++k) led->escaped += P[k];
+                led->escaped_rays++;
+                if (tau[ksoft] < TAU_THIN && tn < r_out) r_out = tn;
+                break;
+            }
+        }
+    }
+    if (s->r_thin_out) s->r_thin_out[src] = r_out;
+    return 0;
+}
+
+/* Checks, the opacity of section 2.2 and the zeroed outputs: the set-up both drivers share. */
+static int32_t run_setup(orc_run* R, const orc_grid* g, const orc_sources* s, const orc_bins* b, const orc_params* p,
+                         double* J, double* gdir, orc_ledger* led)
 {
     if (!g || !s || !b || !p || !J || !led) return -1;
     if (p->correction < 0 || p->correction > 3 || (p->correction && gdir)) return -1;
     if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || b->nbins <= 0 || b->nbins > ORC_MAXB) return -1;
     if (p->level0 < 0 || p->rays_per_cell <= 0) return -1;
-    const int nb = b->nbins;
-    const int32_t nx = g->nx, ny = g->ny, nz = g->nz;
-    const int64_t ncell = (int64_t)nx * ny * nz;
+    memset(R, 0, sizeof(*R));
+    R->g = g;
+    R->s = s;
+    R->b = b;
+    R->p = p;
+    R->nb = b->nbins;
+    R->ncell = (int64_t)g->nx * g->ny * g->nz;
+    const int nb = R->nb;
+    const int64_t ncell = R->ncell;
     const double L = g->cell_cm, y = g->y_he;
 
     /* Optical depth per cell length, per bin (section 2.2: all species). */
@@ -404,192 +628,95 @@ int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, co
             kappa[(int64_t)k * ncell + c] = L * nh * (sg[0] * xhi + y * (sg[1] * xhei + sg[2] * xheii));
         }
     }
+    R->kappa = kappa;
     memset(J, 0, (size_t)nb * (size_t)ncell * sizeof(double));
     if (gdir) memset(gdir, 0, 3 * (size_t)ncell * sizeof(double));
     memset(led, 0, sizeof(*led));
-
-    const int32_t lmax = p->max_level < 0 ? orc_auto_max_level(nx, ny, nz, p->rays_per_cell) : p->max_level;
-    const double tau_term = p->eps_term > 0 ? -log(p->eps_term) : INFINITY;
-    const double V = L * L * L;
+    R->lmax = p->max_level < 0 ? orc_auto_max_level(g->nx, g->ny, g->nz, p->rays_per_cell) : p->max_level;
+    R->tau_term = p->eps_term > 0 ? -log(p->eps_term) : INFINITY;
     /* softest bin: the lowest photon energy (the first of equal ones) */
-    int ksoft = 0;
+    R->ksoft = 0;
     for (int k = 1; k < nb; ++k)
-        if (b->e_erg[k] < b->e_erg[ksoft]) ksoft = k;
-    const double TAU_THIN = 0.1;
-
-    stack_t_ st = {0, 0, 0};
-    for (int32_t src = 0; src < s->n; ++src) {
-        const double* xs = s->pos + 3 * src;
-        double S[ORC_MAXB];
-        for (int k = 0; k < nb; ++k) S[k] = s->ndot[src] * b->frac[k];
-        led->emitted += s->ndot[src];
-
-        /* section 2.6: the optically thin sphere of radius R around the source */
-        double R = 0.0;
-        if (s->r_thin) {
-            R = (double)(float)s->r_thin[src];
-            if (!(R >= 0.0) || !isfinite(R)) goto fail;
-        }
-        if (R > 0.0) {
-            const int64_t lo[3] = {(int64_t)floor(xs[0] - R), (int64_t)floor(xs[1] - R), (int64_t)floor(xs[2] - R)};
-            const int64_t hi[3] = {(int64_t)ceil(xs[0] + R), (int64_t)ceil(xs[1] + R), (int64_t)ceil(xs[2] + R)};
-            for (int64_t cz = lo[2] < 0 ? 0 : lo[2]; cz <= hi[2] && cz < nz; ++cz)
-                for (int64_t cy = lo[1] < 0 ? 0 : lo[1]; cy <= hi[1] && cy < ny; ++cy)
-                    for (int64_t cx = lo[0] < 0 ? 0 : lo[0]; cx <= hi[0] && cx < nx; ++cx) {
-                        const double dx = (double)cx + 0.5 - xs[0], dy = (double)cy + 0.5 - xs[1],
-                                     dz = (double)cz + 0.5 - xs[2];
-                        const double r2 = dx * dx + dy * dy + dz * dz;
-                        if (!(r2 < R * R)) continue;
-                        const double dil = 1.0 / (4.0 * ORC_PI * (r2 > 0.25 ? r2 : 0.25));
-                        const int64_t c = cx + (int64_t)nx * (cy + (int64_t)ny * cz);
-                        for (int k = 0; k < nb; ++k) {
-                            const double a = S[k] * dil;
-                            J[(int64_t)k * ncell + c] += a;
-                            led->absorbed_thin += a * kappa[(int64_t)k * ncell + c];
-                            if (gdir) {
-                                const double nh = g->n_h[c];
-                                const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
-                                for (int sp = 0; sp < 3; ++sp)
-                                    if (ns_[sp] > 0) gdir[(int64_t)sp * ncell + c] += b->sigma[3 * k + sp] * a / (L * L);
-                            }
-                        }
-                    }
-        }
-        double r_out = INFINITY;
-
-        ray_t root;
-        memset(&root, 0, sizeof(root));
-        root.level = p->level0;
-        for (int64_t q = orc_npix(p->level0) - 1; q >= 0; --q) {
-            root.pix = q;
-            if (push(&st, &root)) goto fail;
-        }
-        while (st.n > 0) {
-            const ray_t r = st.v[--st.n];
-            if (tree && led->tree_count < tree_cap)
-                tree[led->tree_count] = ((uint64_t)src << 32) | ((uint64_t)r.level << 28) | (uint64_t)r.pix;
-            led->tree_count++;
-            led->rays++;
-
-            double v[3], d[3];
-            orc_healpix_vec(r.level, r.pix, v);
-            for (int i = 0; i < 3; ++i) d[i] = (double)(float)v[i];
-            double t0 = r.level == p->level0 ? 0.0 : orc_t_split(p->rays_per_cell, r.level - 1);
-            if (R > t0) t0 = R;
-            const double t_end = r.level < lmax ? orc_t_split(p->rays_per_cell, r.level) : INFINITY;
-            if (t0 >= t_end) {
-                /* starts at or beyond its split radius (inside the thin sphere): split at once */
-                ray_t child;
-                memset(&child, 0, sizeof(child));
-                child.level = r.level + 1;
-                for (int q = 3; q >= 0; --q) {
-                    child.pix = 4 * r.pix + q;
-                    if (push(&st, &child)) goto fail;
-                }
-                led->splits++;
-                continue;
-            }
-
-            const double wray = 1.0 / (double)orc_npix(r.level);
-            double P[ORC_MAXB], tau[ORC_MAXB], dtau[ORC_MAXB];
-            for (int k = 0; k < nb; ++k) {
-                tau[k] = r.tau[k];
-                P[k] = S[k] * wray * exp(-tau[k]);
-            }
-            walk_t w;
-            if (!walk_start(&w, xs, d, t0, t_end, nx, ny, nz)) {
-                for (int k = 0; k < nb; ++k) led->escaped += P[k];
-                led->escaped_rays++;
-                if (tau[ksoft] < TAU_THIN && t0 < r_out) r_out = t0;
-                continue;
-            }
-            for (;;) {
-                int at_end, mask;
-                const double tn = walk_next(&w, &at_end, &mask);
-                const double ds = tn - w.t;
-                const int64_t c = w.c[0] + (int64_t)nx * (w.c[1] + (int64_t)ny * w.c[2]);
-                led->crossings++;
-                int64_t cnb = -1;
-                const double fc = p->correction ? orc_correction(&w, w.t, tn, r.level, p->correction, nx, ny, nz, &cnb)
-                                                : 1.0;
-                if (tau[ksoft] < TAU_THIN) {
-                    /* where the softest bin's depth reaches 0.1 inside this crossing */
-                    const double ks = kappa[(int64_t)ksoft * ncell + c];
-                    if (tau[ksoft] + ks * ds >= TAU_THIN) {
-                        const double rc = w.t + (TAU_THIN - tau[ksoft]) / ks;
-                        if (rc < r_out) r_out = rc;
-                    }
-                }
-                for (int k = 0; k < nb; ++k) {
-                    const double kap = kappa[(int64_t)k * ncell + c];
-                    dtau[k] = kap * ds;
-                    const double lost = -expm1(-dtau[k]);        /* 1 - e^-dtau */
-                    orc_deposit(J, kappa, ncell, k, c, P[k] * ds * mean_atten(dtau[k]), fc, cnb);
-                    led->absorbed_trace += P[k] * lost;
-                    if (gdir && dtau[k] > 0) {
-                        /* eq:ion with the absorbed photons split by species optical depth */
-                        const double nh = g->n_h[c];
-                        const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
-                        for (int sp = 0; sp < 3; ++sp) {
-                            if (ns_[sp] <= 0) continue;
-                            const double dts = L * ns_[sp] * b->sigma[3 * k + sp] * ds;
-                            gdir[(int64_t)sp * ncell + c] += P[k] * lost * (dts / dtau[k]) / (V * ns_[sp]);
-                        }
-                    }
-                    P[k] *= exp(-dtau[k]);
-                    tau[k] += dtau[k];
-                }
-                int term = tau_term < INFINITY;
-                for (int k = 0; k < nb && term; ++k)
-                    term = tau[k] >= tau_term && dtau[k] >= ORC_DTAU_TERM_MIN;
-                if (term) {
-                    for (int k = 0; k < nb; ++k) {
-                        const double kap = kappa[(int64_t)k * ncell + c];
-                        orc_deposit(J, kappa, ncell, k, c, P[k] / kap, fc, cnb);
-                        led->absorbed_trace += P[k];
-                        if (gdir) {
-                            const double nh = g->n_h[c];
-                            const double ns_[3] = {nh * g->x_hi[c], y * nh * g->x_hei[c], y * nh * g->x_heii[c]};
-                            for (int sp = 0; sp < 3; ++sp) {
-                                if (ns_[sp] <= 0) continue;
-                                const double ks = L * ns_[sp] * b->sigma[3 * k + sp];
-                                gdir[(int64_t)sp * ncell + c] += P[k] * (ks / kap) / (V * ns_[sp]);
-                            }
-                        }
-                    }
-                    led->terminated++;
-                    break;
-                }
-                if (at_end) {
-                    ray_t child;
-                    memset(&child, 0, sizeof(child));
-                    child.level = r.level + 1;
-                    for (int k = 0; k < nb; ++k) child.tau[k] = tau[k];
-                    for (int q = 3; q >= 0; --q) {
-                        child.pix = 4 * r.pix + q;
-                        if (push(&st, &child)) goto fail;
-                    }
-                    led->splits++;
-                    break;
-                }
-                walk_advance(&w, mask, tn);
-                if (!walk_inside(&w, nx, ny, nz)) {
-                    for (int k = 0; k < nb; ++k) led->escaped += P[k];
-                    led->escaped_rays++;
-                    if (tau[ksoft] < TAU_THIN && tn < r_out) r_out = tn;
-                    break;
-                }
-            }
-        }
-        if (s->r_thin_out) s->r_thin_out[src] = r_out;
-    }
-    free(st.v);
-    free(kappa);
+        if (b->e_erg[k] < b->e_erg[R->ksoft]) R->ksoft = k;
     return 0;
-fail:
+}
+
+int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, const orc_params* p,
+                  double* J, double* gdir, uint64_t* tree, int64_t tree_cap, orc_ledger* led)
+{
+    orc_run R;
+    if (run_setup(&R, g, s, b, p, J, gdir, led)) return -1;
+    stack_t_ st = {0, 0, 0};
+    int32_t rc = 0;
+    for (int32_t src = 0; src < s->n && rc == 0; ++src) rc = trace_source(&R, src, J, gdir, tree, tree_cap, led, &st);
     free(st.v);
-    free(kappa);
-    return -1;
+    free((void*)R.kappa);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* The same trace on several host threads (for timing the oracle on every core).     */
+/* ------------------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_run* R;
+    double* J;
+    int32_t first, stride;
+    orc_ledger led;
+    int32_t rc;
+} mt_part;
+
+static void* mt_worker(void* arg)
+{
+    mt_part* w = (mt_part*)arg;
+    stack_t_ st = {0, 0, 0};
+    memset(&w->led, 0, sizeof(w->led));
+    w->rc = 0;
+    for (int32_t src = w->first; src < w->R->s->n && w->rc == 0; src += w->stride)
+        w->rc = trace_source(w->R, src, w->J, NULL, NULL, 0, &w->led, &st);
+    free(st.v);
+    return NULL;
+}
+
+int32_t orc_trace_mt(const orc_grid* g, const orc_sources* s, const orc_bins* b, const orc_params* p, double* J,
+                     int32_t nthreads, orc_ledger* led)
+{
+    if (nthreads < 1 || nthreads > 1024) return -1;
+    orc_run R;
+    if (run_setup(&R, g, s, b, p, J, NULL, led)) return -1;
+    R.atomic = nthreads > 1;
+    mt_part* parts = (mt_part*)calloc((size_t)nthreads, sizeof(mt_part));
+    pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    int32_t rc = parts && th ? 0 : -1;
+    int started = 0;
+    for (int t = 0; t < nthreads && rc == 0; ++t) {
+        parts[t].R = &R;
+        parts[t].J = J;
+        parts[t].first = t;
+        parts[t].stride = nthreads;
+        if (pthread_create(&th[t], NULL, mt_worker, &parts[t]) != 0) rc = -1;
+        else ++started;
+    }
+    for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    /* the ledgers in thread order */
+    for (int t = 0; t < started && rc == 0; ++t) {
+        const orc_ledger* q = &parts[t].led;
+        if (parts[t].rc) rc = -1;
+        led->emitted += q->emitted;
+        led->absorbed_trace += q->absorbed_trace;
+        led->escaped += q->escaped;
+        led->absorbed_thin += q->absorbed_thin;
+        led->crossings += q->crossings;
+        led->rays += q->rays;
+        led->splits += q->splits;
+        led->terminated += q->terminated;
+        led->escaped_rays += q->escaped_rays;
+        led->tree_count += q->tree_count;
+    }
+    free(parts);
+    free(th);
+    free((void*)R.kappa);
+    return rc;
 }
 
 void orc_finalize(const orc_grid* g, const orc_bins* b, const double* J, double* gamma, double* heat,

@@ -103,6 +103,13 @@ int64_t orc_walk(int32_t nx, int32_t ny, int32_t nz, const double xs[3], const d
 int32_t orc_trace(const orc_grid* g, const orc_sources* s, const orc_bins* b, const orc_params* p,
                   double* J, double* gdir, uint64_t* tree, int64_t tree_cap, orc_ledger* led);
 
+/* orc_trace with the sources split over nthreads host threads (source i on thread
+ * i mod nthreads), adding into the one field J with atomic compare-and-swap additions:
+ * equal to orc_trace up to the order of the floating-point additions. No direct rates or
+ * ray tree. For timing the oracle on every core of a host. */
+int32_t orc_trace_mt(const orc_grid* g, const orc_sources* s, const orc_bins* b, const orc_params* p, double* J,
+                     int32_t nthreads, orc_ledger* led);
+
 /* Rates from J (eq:ion per bin with the species split, section 2.8 heating):
  *   gamma[S][c] = sum_b sigma_{b,S} J_b[c] / L^2                      [1/s]
  *   heat[S][c]  = sum_b sigma_{b,S} (E_b - E_S)^+ J_b[c] / L^2        [erg/s]

@@ -183,3 +183,19 @@ def golden():
 
     with open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")) as f:
         return json.load(f)
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_threaded_oracle_equals_single_thread(threads):
+    """The oracle on several host threads (used to time it on every core): the same field
+    and ledger up to the order of the floating-point additions."""
+    w = W.lognormal(24, 7, seed=13, source_cells="uniform")
+    w.sources["r_thin"] = np.array([0.0, 2.5, 0.0, 0.7, 4.0, 0.0, 1.25])
+    one = oracle.trace(w.grid, w.sources, w.bins, dict(w.trace, correction=2))
+    many = oracle.trace_mt(w.grid, w.sources, w.bins, dict(w.trace, correction=2), threads)
+    np.testing.assert_allclose(many["J"], one["J"], rtol=1e-13, atol=1e-300)
+    np.testing.assert_array_equal(many["r_thin_out"], one["r_thin_out"])
+    for k in ("crossings", "rays", "splits", "terminated", "escaped_rays"):
+        assert many["ledger"][k] == one["ledger"][k], k
+    for k in ("emitted", "absorbed_trace", "escaped", "absorbed_thin"):
+        assert many["ledger"][k] == pytest.approx(one["ledger"][k], rel=1e-10), k  # sums of ~1e6 terms
