@@ -69,11 +69,25 @@ typedef struct {
 } arc_grid;
 
 /* Point sources (section 2.1: source positions; section 2.4: photon rate per bin).
- * Host pointers. Positions must lie on the 2^-12 cell lattice inside [0, n). */
+ * Host pointers. Positions must lie on the 2^-12 cell lattice inside [0, n).
+ *
+ * Optically thin approximation (section 2.6), optional. r_thin[i] > 0 (used rounded to
+ * float, below 2^20 cells) is source i's thin radius R, normally the R_tau<0.1 measured by
+ * the previous trace: every cell whose centre lies within R of the source receives the
+ * point-source field S_b / (4 pi r^2) (r the centre's distance, at least half a cell), and
+ * the source's rays start at radius R with zero optical depth (a ray whose split radius
+ * does not lie beyond R splits at once, without a crossing). r_thin_out, if set, receives
+ * each source's R_tau<0.1 of this trace: the least path length at which a ray's optical depth
+ * in the bin of lowest photon energy reaches 0.1, a ray that leaves the grid (or starts
+ * outside it) below 0.1 counting with its length there; +inf when no ray of the source
+ * measures one. Either one needs ARC_PREC_FP32_COMP (else ARC_E_UNSUPPORTED); a radius that
+ * is negative, not finite or not below 2^20 gives ARC_E_RANGE. */
 typedef struct {
     int32_t n;
     const double* pos;  /* [n][3] x, y, z in cell units */
     const double* ndot; /* [n] ionising photons per second, escape fraction applied */
+    const double* r_thin; /* [n] thin radius per source [cells], or NULL (no thin sphere) */
+    double* r_thin_out; /* [n] out: R_tau<0.1 per source [cells], or NULL (not measured) */
 } arc_sources;
 
 /* Frequency bins (section 2.2): one frequency per bin standing for the bin-averaged
@@ -126,6 +140,9 @@ typedef struct {
                               results are identical to 0 */
     int32_t correction;    /* geometric correction (section 2.5), ARC_CORR_*; needs
                               ARC_PREC_FP32_COMP (else ARC_E_UNSUPPORTED) */
+    int32_t spill_cap;     /* batched: ray records of each wave's spill area in device memory
+                              (0 = 4096; < 0 = ARC_E_ARG). Rays that do not fit are dropped and
+                              the call returns ARC_E_QUEUE. */
 } arc_trace_params;
 
 /* Geometric correction (section 2.5). D_edge: distance from a crossing's midpoint to the
@@ -133,11 +150,12 @@ typedef struct {
  * cell keeps f_c = 1/2 + D_edge / L_Pix of the crossing's photons when D_edge < L_Pix / 2
  * (eq:correction). ARC_CORR_CONSERVING also deposits the rest in the neighbour across that
  * face, at the neighbour's opacity (eq:correction2, the absorber ratio taken per bin as the
- * opacity ratio), so photons are conserved; the cell keeps the share when that neighbour is
- * outside the grid or has less than 1/16 of its opacity in the bin. Faces within 1e-9
- * cell of each other count as tied (lower axis, then lower face). The other two modes
- * drop the removed share. With ARC_CORR_CONSERVING the fixed-point unit is 49 times
- * coarser (a cell may also receive shares from its six neighbours). */
+ * opacity ratio), so photons are conserved, whatever the ratio; the cell keeps the share
+ * when that neighbour is outside the grid or has no absorber of the bin (zero opacity).
+ * The moved photons are held in a second fixed-point field of two 64-bit limbs per bin
+ * (units 2^20 u_J,b and 2^-12 u_J,b) and divided by the receiving cell's opacity when the
+ * rates are formed. Faces within 1e-9 cell of each other count as tied (lower axis, then
+ * lower face). The other two modes drop the removed share. */
 #define ARC_CORR_NONE 0
 #define ARC_CORR_FC 1           /* f_c alone */
 #define ARC_CORR_CONSERVING 2   /* f_c plus the secondary deposit: the paper's choice */
@@ -165,6 +183,9 @@ typedef struct {
     double ms_trace;       /* device time of the trace kernels [ms] */
     double ms_total;       /* device time of the whole call [ms] */
     double ms_kernel;      /* batched: device time of the persistent trace kernel [ms] */
+    double absorbed_thin;  /* part of `absorbed` deposited by the optically thin fill
+                              (section 2.6); the rays alone conserve photons:
+                              emitted = (absorbed - absorbed_thin) + escaped */
 } arc_ledger;
 
 /* One ray-tracing pass (a whole RT step's radiation field). `out` receives the rates;
@@ -198,7 +219,11 @@ arc_status arc_autotune(arc_ctx* ctx, const arc_grid* grid, const arc_sources* s
                         double dt, const arc_trace_params* params, arc_rates* out, arc_tune_result* result);
 
 /* Copy the fixed-point field of the last arc_trace, [nbins][ncell] int64 in units of
- * ledger.u_j[b], into the device array `dst` (caller-owned, nbins * ncell entries). */
+ * ledger.u_j[b], into the device array `dst` (caller-owned, nbins * ncell entries). If the
+ * last trace used ARC_CORR_CONSERVING, dst must hold 3 * nbins * ncell entries: the field is
+ * followed by the moved-photon field's low limb [nbins][ncell] (units 2^-12 u_j[b]) and its
+ * high limb [nbins][ncell] (units 2^20 u_j[b]); a cell's rate field is then
+ * J + (high 2^20 + low 2^-12) / kappa, kappa its opacity per cell length. */
 arc_status arc_get_field(arc_ctx* ctx, int64_t* dst, int64_t count, void* stream);
 
 /* FP32 HEALPix pixel centres of `level` (nested order) as used by the tracer, written

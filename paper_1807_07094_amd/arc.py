@@ -37,7 +37,8 @@ class Grid(C.Structure):
 
 
 class Sources(C.Structure):
-    _fields_ = [("n", C.c_int32), ("pos", C.c_void_p), ("ndot", C.c_void_p)]
+    _fields_ = [("n", C.c_int32), ("pos", C.c_void_p), ("ndot", C.c_void_p), ("r_thin", C.c_void_p),
+                ("r_thin_out", C.c_void_p)]
 
 
 class Bins(C.Structure):
@@ -51,7 +52,7 @@ class TraceParams(C.Structure):
                 ("stream", C.c_void_p), ("tune_waves", C.c_int32), ("tune_blocks", C.c_int32),
                 ("tune_refill", C.c_int32), ("tune_item_level", C.c_int32), ("tree_out", C.c_void_p),
                 ("tree_cap", C.c_int64), ("u_j_override", C.c_double), ("graph", C.c_int32),
-                ("correction", C.c_int32)]
+                ("correction", C.c_int32), ("spill_cap", C.c_int32)]
 
 
 class TuneResult(C.Structure):
@@ -69,7 +70,7 @@ class Ledger(C.Structure):
                 ("crossings", C.c_uint64), ("rays", C.c_uint64), ("splits", C.c_uint64),
                 ("terminated", C.c_uint64), ("escaped_rays", C.c_uint64), ("spills", C.c_uint64),
                 ("tree_count", C.c_int64), ("u_j", C.c_double * 4), ("ms_trace", C.c_double),
-                ("ms_total", C.c_double), ("ms_kernel", C.c_double)]
+                ("ms_total", C.c_double), ("ms_kernel", C.c_double), ("absorbed_thin", C.c_double)]
 
 
 class ChemParams(C.Structure):
@@ -206,34 +207,46 @@ class Context:
 
     @staticmethod
     def _trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term, precision, schedule, stream,
-                    tree, tune_waves, tune_blocks, tune_refill, tune_item_level, u_j_override, graph, correction=0):
+                    tree, tune_waves, tune_blocks, tune_refill, tune_item_level, u_j_override, graph, correction=0,
+                    spill_cap=0):
         g = _grid(grid)
         pos = np.ascontiguousarray(sources["pos"], np.float64).reshape(-1, 3)
         ndot = np.ascontiguousarray(sources["ndot"], np.float64).reshape(-1)
+        # optically thin approximation (section 2.6): radii in, measured radii out (written in
+        # place into sources["r_thin_out"], a float64 array of one entry per source)
+        r_thin = sources.get("r_thin")
+        r_thin = np.ascontiguousarray(r_thin, np.float64).reshape(-1) if r_thin is not None else None
+        r_out = sources.get("r_thin_out")
+        if r_thin is not None and r_thin.size != ndot.size:
+            raise ValueError("r_thin needs one radius per source")
+        if r_out is not None and (not isinstance(r_out, np.ndarray) or r_out.dtype != np.float64 or
+                                  r_out.size != ndot.size or not r_out.flags.c_contiguous):
+            raise ValueError("r_thin_out must be a contiguous float64 array with one entry per source")
         frac = np.ascontiguousarray(bins["frac"], np.float64)
         e = np.ascontiguousarray(bins["e_erg"], np.float64)
         sig = np.ascontiguousarray(bins["sigma"], np.float64).reshape(-1, 3)
         thr = np.ascontiguousarray(bins["e_thr"], np.float64)
-        s = Sources(ndot.size, _ptr(pos), _ptr(ndot))
+        s = Sources(ndot.size, _ptr(pos), _ptr(ndot), _ptr(r_thin), _ptr(r_out))
         b = Bins(frac.size, _ptr(frac), _ptr(e), _ptr(sig), _ptr(thr))
         p = TraceParams(int(level0), int(max_level), float(rays_per_cell), float(eps_term),
                         PREC[precision] if isinstance(precision, str) else int(precision),
                         SCHED[schedule] if isinstance(schedule, str) else int(schedule), _stream(stream),
                         int(tune_waves), int(tune_blocks), int(tune_refill), int(tune_item_level), _ptr(tree),
                         int(tree.numel()) if tree is not None else 0, float(u_j_override), int(bool(graph)),
-                        CORR[correction] if isinstance(correction, str) else int(correction))
+                        CORR[correction] if isinstance(correction, str) else int(correction), int(spill_cap))
         # the host arrays must outlive the call: keep them with the structures
-        return g, s, b, p, (pos, ndot, frac, e, sig, thr)
+        return g, s, b, p, (pos, ndot, frac, e, sig, thr, r_thin, r_out)
 
     def trace(self, grid, sources: dict, bins: dict, dt: float, gamma, heat, level0=1, rays_per_cell=4.0,
               max_level=-1, eps_term=1e-6, precision="fp32_comp", schedule="batched", stream=None, tree=None,
               tune_waves=0, tune_blocks=0, tune_refill=0, tune_item_level=0, u_j_override=0.0, graph=False,
-              correction="none") -> dict:
+              correction="none", spill_cap=0) -> dict:
         """arc_trace. gamma/heat: device float32 tensors of shape [3, nz, ny, nx]. correction:
-        "none", "fc", "conserving" or "fc_squared" (section 2.5)."""
+        "none", "fc", "conserving" or "fc_squared" (section 2.5). sources may carry "r_thin" and
+        "r_thin_out" (section 2.6)."""
         g, s, b, p, _keep = self._trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term,
                                              precision, schedule, stream, tree, tune_waves, tune_blocks, tune_refill,
-                                             tune_item_level, u_j_override, graph, correction)
+                                             tune_item_level, u_j_override, graph, correction, spill_cap)
         r = Rates(_ptr(gamma), _ptr(heat))
         led = Ledger()
         self._check(lib().arc_trace(self._h, C.byref(g), C.byref(s), C.byref(b), float(dt), C.byref(p),
@@ -255,7 +268,9 @@ class Context:
         return {k: getattr(res, k) for k, _ in TuneResult._fields_}
 
     def get_field(self, dst, stream=None):
-        """arc_get_field into a device int64 tensor of nbins * ncell entries."""
+        """arc_get_field into a device int64 tensor of nbins * ncell entries (3 * nbins * ncell
+        after a trace with the conserving correction: the field, then the moved-photon field's
+        low and high limbs)."""
         self._check(lib().arc_get_field(self._h, _ptr(dst), int(dst.numel()), _stream(stream)))
         return dst
 

@@ -29,11 +29,15 @@ struct arc_ctx {
     size_t kappa_bytes = 0;
     unsigned long long* J = nullptr;   // [cell][nbp]
     size_t J_bytes = 0;
+    unsigned long long* M = nullptr;   // conserving correction: moved photons, [cell][2][nbp]
+    size_t M_bytes = 0;
     // source table
     SourceRec* src = nullptr;
     double* src_pos = nullptr;
     double* src_ndot = nullptr;
     uint32_t* src_order = nullptr;
+    double* src_rthin = nullptr;       // optically thin radius per source (section 2.6)
+    uint32_t* r_out = nullptr;         // measured R_tau<0.1 per source (FP32 bits)
     int src_cap = 0;
     // HEALPix centres, levels 0..dirs_levels-1
     float4* dirs = nullptr;
@@ -58,6 +62,7 @@ struct arc_ctx {
     // last trace
     int last_nb = 0, last_nbp = 0, last_nx = 0, last_ny = 0, last_nbx8 = 0, last_nby8 = 0;
     size_t last_ncell = 0;
+    bool last_moved = false;  // the last trace filled M
     bool have_field = false;
     // replayed launches of the batched schedule: [0] set-up, [1] the first levels, [2] the
     // persistent trace, [3] the rates; valid while the launch arguments equal graph_key
@@ -256,8 +261,9 @@ void arc_destroy(arc_ctx* c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    void* bufs[] = {c->kappa, c->J, c->src, c->src_pos, c->src_ndot, c->src_order, c->dirs, c->rays[0], c->rays[1],
-                    c->spill, c->counters, c->acc, c->u32, c->errflag, c->chem_stats, c->reject};
+    void* bufs[] = {c->kappa, c->J, c->M, c->src, c->src_pos, c->src_ndot, c->src_order, c->src_rthin, c->r_out,
+                    c->dirs, c->rays[0], c->rays[1], c->spill, c->counters, c->acc, c->u32, c->errflag,
+                    c->chem_stats, c->reject};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     for (int i = 0; i < 6; ++i)
@@ -290,9 +296,12 @@ struct TracePlan {
     OpacityArgs oa;
     TraceArgs A;
     FinalizeArgs fa;
+    ThinFillArgs tf;
+    int thin;        // optically thin approximation in use (section 2.6)
     int precision;
     // batched schedule
     int waves, blocks, refill, litem;
+    int spill_cap_req;  // records of each wave's spill area (0: 4096)
     double n_roots;
     size_t cap[2];  // records of rays0 / rays1
     uint32_t spill_cap;
@@ -329,6 +338,21 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
         return fail(c, ARC_E_ARG, "bad correction mode %d", p->correction);
     if (p->correction != ARC_CORR_NONE && p->precision != ARC_PREC_FP32_COMP)
         return fail(c, ARC_E_UNSUPPORTED, "the geometric correction needs ARC_PREC_FP32_COMP");
+    if (p->spill_cap < 0) return fail(c, ARC_E_ARG, "spill_cap must be >= 0");
+    // optically thin approximation (section 2.6): per-source start radii and/or the measured
+    // R_tau<0.1
+    bool thin = s->r_thin_out != nullptr;
+    double max_r = 0.0;
+    if (s->r_thin)
+        for (int i = 0; i < s->n; ++i) {
+            const double r = s->r_thin[i];
+            if (!(r >= 0.0) || !(r < 1048576.0))
+                return fail(c, ARC_E_RANGE, "r_thin[%d] must be finite, >= 0 and below 2^20 cells", i);
+            thin = thin || r > 0.0;
+            max_r = std::max(max_r, (double)(float)r);
+        }
+    if (thin && p->precision != ARC_PREC_FP32_COMP)
+        return fail(c, ARC_E_UNSUPPORTED, "the optically thin approximation needs ARC_PREC_FP32_COMP");
 
     hipStream_t st = (hipStream_t)p->stream;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -347,19 +371,21 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     P.nbz8 = nbz8;
     P.nsrc = s->n;
     P.precision = p->precision;
+    P.thin = thin ? 1 : 0;
+    P.spill_cap_req = p->spill_cap;
 
     // Fixed-point unit per bin. One source deposits at most sqrt(3) S_b into a cell
     // (the photon rate through any sphere is at most S_b and a cell is at most sqrt(3)
-    // long), plus a remainder below eps_term S_b sqrt(3) / 0.01 on termination. The sum
-    // over sources therefore stays below 2^62 units. With the conserving geometric
-    // correction a cell also receives at most half of each neighbour's crossing, times at
-    // most 16 (the opacity-ratio bound), from each of its six neighbours: 1 + 6 * 8 = 49.
+    // long), plus a remainder below eps_term S_b sqrt(3) / 0.01 on termination, plus with
+    // the optically thin fill at most S_b / pi (r >= 1/2). The sum over sources therefore
+    // stays below 2^62 units. The moved photons of the conserving correction are counted in
+    // the same unit: all of them together are at most the photons emitted.
     for (int k = 0; k < kMaxBins; ++k) P.uj[k] = 1.0;
-    const double corr_factor = p->correction == ARC_CORR_CONSERVING ? 49.0 : 1.0;
     for (int i = 0; i < s->n; ++i) P.sum_ndot += s->ndot[i];
     for (int k = 0; k < nb; ++k) {
-        const double bound = (std::sqrt(3.0) + p->eps_term * std::sqrt(3.0) / (double)kDtauTermMin) * P.sum_ndot *
-                             b->frac[k] * (1.0 + 1e-6) * corr_factor;
+        const double bound = (std::sqrt(3.0) + p->eps_term * std::sqrt(3.0) / (double)kDtauTermMin +
+                              (thin ? 1.0 / M_PI : 0.0)) *
+                             P.sum_ndot * b->frac[k] * (1.0 + 1e-6);
         const double need = bound / 4611686018427387904.0;  // 2^62
         if (p->u_j_override > 0) {
             if (p->u_j_override < need)
@@ -377,19 +403,22 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
         const size_t kb = nblocked * (nb == 1 ? sizeof(float) : sizeof(float4));
         HIP_TRY(c, grow(&c->kappa, &c->kappa_bytes, kb));
         HIP_TRY(c, grow(&c->J, &c->J_bytes, nblocked * nbp * sizeof(unsigned long long)));
+        if (p->correction == ARC_CORR_CONSERVING)
+            HIP_TRY(c, grow(&c->M, &c->M_bytes, nblocked * 2 * nbp * sizeof(unsigned long long)));
         if (s->n > c->src_cap) {
-            if (c->src) HIP_TRY(c, hipFree(c->src));
-            if (c->src_pos) HIP_TRY(c, hipFree(c->src_pos));
-            if (c->src_ndot) HIP_TRY(c, hipFree(c->src_ndot));
-            if (c->src_order) HIP_TRY(c, hipFree(c->src_order));
+            void* old[] = {c->src, c->src_pos, c->src_ndot, c->src_order, c->src_rthin, c->r_out};
+            for (void* q : old)
+                if (q) HIP_TRY(c, hipFree(q));
             c->src = nullptr;
-            c->src_pos = c->src_ndot = nullptr;
-            c->src_order = nullptr;
+            c->src_pos = c->src_ndot = c->src_rthin = nullptr;
+            c->src_order = c->r_out = nullptr;
             c->src_cap = 0;
             HIP_TRY(c, hipMalloc((void**)&c->src, s->n * sizeof(SourceRec)));
             HIP_TRY(c, hipMalloc((void**)&c->src_pos, s->n * 3 * sizeof(double)));
             HIP_TRY(c, hipMalloc((void**)&c->src_ndot, s->n * sizeof(double)));
             HIP_TRY(c, hipMalloc((void**)&c->src_order, s->n * sizeof(uint32_t)));
+            HIP_TRY(c, hipMalloc((void**)&c->src_rthin, s->n * sizeof(double)));
+            HIP_TRY(c, hipMalloc((void**)&c->r_out, s->n * sizeof(uint32_t)));
             c->src_cap = s->n;
         }
     }
@@ -415,6 +444,7 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     oa.kappa1 = nb == 1 ? (float*)c->kappa : nullptr;
     oa.kappa4 = nb == 1 ? nullptr : (float4*)c->kappa;
     oa.J = c->J;
+    oa.M = p->correction == ARC_CORR_CONSERVING ? c->M : nullptr;
     oa.nbp = nbp;
     oa.errflag = c->errflag;
 
@@ -442,6 +472,12 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     A.tree = (unsigned long long*)p->tree_out;
     A.tree_cap = p->tree_out ? p->tree_cap : 0;
     A.corr = p->correction;
+    A.M = oa.M;
+    // softest bin: the lowest photon energy (the first of equal ones)
+    A.ksoft = 0;
+    for (int k = 1; k < nb; ++k)
+        if (b->e_erg[k] < b->e_erg[A.ksoft]) A.ksoft = k;
+    A.r_out = thin ? c->r_out : nullptr;
 
     FinalizeArgs& fa = P.fa;
     fa.nb = nb;
@@ -463,11 +499,40 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
         }
     }
     fa.J = c->J;
+    fa.M = oa.M;
     fa.kappa1 = oa.kappa1;
     fa.kappa4 = oa.kappa4;
     fa.gamma = out->gamma;
     fa.heat = out->heat;
     fa.absorbed = c->acc + 4;
+
+    if (thin) {
+        ThinFillArgs& tf = P.tf;
+        tf.nb = nb;
+        tf.nbp = nbp;
+        tf.nsrc = s->r_thin && max_r > 0.0 ? s->n : 0;
+        // blocks per source: about 8192 cells of the largest bounding box each, a power of two
+        const double box = std::pow(2.0 * max_r + 2.0, 3.0);
+        int parts = 1;
+        while (parts < 1024 && (double)parts * 8192.0 < box) parts *= 2;
+        tf.parts = parts;
+        tf.nx = g->nx;
+        tf.ny = g->ny;
+        tf.nz = g->nz;
+        tf.nbx8 = nbx8;
+        tf.nby8 = nby8;
+        tf.pos = c->src_pos;
+        tf.ndot = c->src_ndot;
+        tf.r_thin = c->src_rthin;
+        for (int k = 0; k < nb; ++k) {
+            tf.coef[k] = b->frac[k] / (4.0 * M_PI * P.uj[k]);
+            tf.uj[k] = P.uj[k];
+        }
+        tf.J = c->J;
+        tf.kappa1 = oa.kappa1;
+        tf.kappa4 = oa.kappa4;
+        tf.absorbed_thin = c->acc + 5;
+    }
     return ARC_OK;
 }
 
@@ -511,7 +576,7 @@ arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int re
         need[(l - level0) & 1] = std::max(need[(l - level0) & 1], (size_t)rays_at(l));
     for (int i = 0; i < 2; ++i)
         if (need[i] > c->rcap[i]) HIP_TRY(c, grow_rays(c, i, need[i]));
-    const uint32_t spill_cap = 4096;
+    const uint32_t spill_cap = P.spill_cap_req > 0 ? (uint32_t)P.spill_cap_req : 4096u;
     const size_t spill_need = (size_t)blocks * waves * spill_cap;
     if (spill_need > c->spill_entries) {
         size_t cap_bytes = c->spill_entries * sizeof(RayRec);
@@ -543,8 +608,14 @@ hipError_t enqueue_common(arc_ctx* c, const TracePlan& P, hipStream_t st)
     if ((e = launch_zero_f64(c->acc, 8, st)) != hipSuccess) return e;
     if ((e = launch_set_u32((uint32_t*)c->errflag, 0u, st)) != hipSuccess) return e;
     if ((e = launch_opacity(P.oa, st)) != hipSuccess) return e;
-    if (P.nsrc > 0 && (e = launch_sources(P.nsrc, c->src_pos, c->src_ndot, P.src_scale, P.nb, c->src, st)) != hipSuccess)
+    if (P.nsrc > 0 && (e = launch_sources(P.nsrc, c->src_pos, c->src_ndot, P.thin ? c->src_rthin : nullptr,
+                                          P.src_scale, P.nb, c->src, st)) != hipSuccess)
         return e;
+    if (P.thin) {
+        // no ray measured yet: R_tau<0.1 = +inf
+        if ((e = launch_fill_u32(c->r_out, (uint32_t)P.nsrc, 0x7F800000u, st)) != hipSuccess) return e;
+        if ((e = launch_thin_fill(P.tf, st)) != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 
@@ -677,6 +748,12 @@ arc_status run_trace(arc_ctx* c, const TracePlan& P, const arc_sources* s, doubl
     if (s->n > 0) {
         HIP_TRY(c, hipMemcpyAsync(c->src_pos, s->pos, s->n * 3 * sizeof(double), hipMemcpyHostToDevice, st));
         HIP_TRY(c, hipMemcpyAsync(c->src_ndot, s->ndot, s->n * sizeof(double), hipMemcpyHostToDevice, st));
+        if (P.thin) {
+            if (s->r_thin)
+                HIP_TRY(c, hipMemcpyAsync(c->src_rthin, s->r_thin, s->n * sizeof(double), hipMemcpyHostToDevice, st));
+            else
+                HIP_TRY(c, launch_zero_f64(c->src_rthin, (size_t)s->n, st));
+        }
         if (batched) {
             // the work queue starts with the brightest sources, whose rays travel furthest, so
             // that the longest subtrees are not the last ones taken (the field does not depend
@@ -725,10 +802,18 @@ arc_status run_trace(arc_ctx* c, const TracePlan& P, const arc_sources* s, doubl
     unsigned long long cnt[kNumCounters];
     double acc[8];
     int errflag = 0;
+    std::vector<uint32_t> rbits(P.thin && s->r_thin_out ? (size_t)s->n : 0);
     HIP_TRY(c, hipMemcpyAsync(cnt, c->counters, sizeof cnt, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(acc, c->acc, sizeof acc, hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipMemcpyAsync(&errflag, c->errflag, sizeof errflag, hipMemcpyDeviceToHost, st));
+    if (!rbits.empty())
+        HIP_TRY(c, hipMemcpyAsync(rbits.data(), c->r_out, rbits.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(c, hipStreamSynchronize(st));
+    for (size_t i = 0; i < rbits.size(); ++i) {
+        float r;
+        std::memcpy(&r, &rbits[i], sizeof r);
+        s->r_thin_out[i] = (double)r;
+    }
 
     c->last_nb = P.nb;
     c->last_nbp = P.nbp;
@@ -737,6 +822,7 @@ arc_status run_trace(arc_ctx* c, const TracePlan& P, const arc_sources* s, doubl
     c->last_ny = P.A.ny;
     c->last_nbx8 = P.nbx8;
     c->last_nby8 = P.nby8;
+    c->last_moved = P.A.M != nullptr;
     c->have_field = true;
     if (errflag) return fail(c, ARC_E_RANGE, "grid values out of range (n_h <= 0, fraction outside [0,1] or non-finite)");
     if (cnt[kQueueOverflow]) return fail(c, ARC_E_QUEUE, "ray queue capacity exceeded (%llu rays dropped)", cnt[kQueueOverflow]);
@@ -747,6 +833,7 @@ arc_status run_trace(arc_ctx* c, const TracePlan& P, const arc_sources* s, doubl
         for (int k = 0; k < P.nb; ++k) esc += acc[k] * P.uj[k];
         ledger->escaped = esc * dt;
         ledger->absorbed = acc[4] * dt;
+        ledger->absorbed_thin = acc[5] * dt;
         ledger->crossings = cnt[kCrossings];
         ledger->rays = cnt[kRays];
         ledger->splits = cnt[kSplits];
@@ -806,12 +893,14 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
         if (!t) {
             // tune on an evenly spaced subset of at most 256 sources
             const int step = std::max(1, (s->n + 255) / 256);
-            std::vector<double> pos, nd;
+            std::vector<double> pos, nd, rt;
             for (int i = 0; i < s->n; i += step) {
                 pos.insert(pos.end(), s->pos + 3 * i, s->pos + 3 * i + 3);
                 nd.push_back(s->ndot[i]);
+                if (s->r_thin) rt.push_back(s->r_thin[i]);
             }
-            const arc_sources sub{(int32_t)nd.size(), pos.data(), nd.data()};
+            const arc_sources sub{(int32_t)nd.size(), pos.data(), nd.data(), s->r_thin ? rt.data() : nullptr,
+                                  nullptr};
             if ((rc = autotune_impl(c, g, &sub, b, dt, p, out, &fresh)) != ARC_OK) return rc;
             t = &fresh;
             // the tuning runs changed the plan's buffers: plan again for all sources
@@ -866,7 +955,9 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
             best = std::min(best, led.ms_trace);
         }
         HIP_TRY(c, launch_zero_u64(c->sums, 2, st));
-        HIP_TRY(c, launch_field_checksum(c->J, (size_t)P.nbx8 * P.nby8 * P.nbz8 * 512 * P.nbp, c->sums, st));
+        const size_t words = (size_t)P.nbx8 * P.nby8 * P.nbz8 * 512 * P.nbp;
+        HIP_TRY(c, launch_field_checksum(c->J, words, c->sums, st));
+        if (P.A.M) HIP_TRY(c, launch_field_checksum(P.A.M, 2 * words, c->sums, st));
         unsigned long long h[2];
         HIP_TRY(c, hipMemcpyAsync(h, c->sums, sizeof h, hipMemcpyDeviceToHost, st));
         HIP_TRY(c, hipStreamSynchronize(st));
@@ -949,11 +1040,13 @@ arc_status arc_get_field(arc_ctx* c, int64_t* dst, int64_t count, void* stream)
 {
     if (!c || !dst) return ARC_E_ARG;
     if (!c->have_field) return fail(c, ARC_E_ARG, "no field: call arc_trace first");
-    if (count < (int64_t)(c->last_ncell * c->last_nb)) return fail(c, ARC_E_ARG, "dst too small");
+    const int64_t parts = c->last_moved ? 3 : 1;
+    if (count < parts * (int64_t)(c->last_ncell * c->last_nb))
+        return fail(c, ARC_E_ARG, "dst too small (needs %lld entries)", (long long)(parts * c->last_ncell * c->last_nb));
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, launch_get_field(c->J, c->last_nb, c->last_nbp, c->last_nx, c->last_ny, c->last_nbx8, c->last_nby8,
-                                (uint32_t)c->last_ncell, (long long*)dst, st));
+    HIP_TRY(c, launch_get_field(c->J, c->last_moved ? c->M : nullptr, c->last_nb, c->last_nbp, c->last_nx,
+                                c->last_ny, c->last_nbx8, c->last_nby8, (uint32_t)c->last_ncell, (long long*)dst, st));
     HIP_TRY(c, hipStreamSynchronize(st));
     return ARC_OK;
 }

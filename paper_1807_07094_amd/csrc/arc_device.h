@@ -52,7 +52,8 @@ enum Counter : int {
 // Per-source constants (section 2.1 keeps the source position on chip; here it is a
 // 32-byte record read through L2 once per ray).
 struct __align__(16) SourceRec {
-    float x, y, z, pad;   // position on the 2^-12 lattice (exact in FP32 up to 2048 cells)
+    float x, y, z;        // position on the 2^-12 lattice (exact in FP32 up to 2048 cells)
+    float r_thin;         // optically thin radius (section 2.6): rays start at this radius
     float scale[4];       // ndot * frac_b / (12 * u_J,b): root-ray photon rate in field units
 };
 
@@ -93,7 +94,17 @@ struct TraceArgs {
     unsigned long long* tree;  // optional record of every ray traced
     long long tree_cap;
     int corr;                  // geometric correction: 0 none, 1 f_c, 2 f_c + secondary, 3 f_c^2
+    // corr == 2: photons moved into a cell by the secondary correction (eq:correction2), in two
+    // limbs per bin, [cell][limb][nbp]: limb 0 in units of 2^20 u_J,b, limb 1 in units of
+    // 2^-12 u_J,b
+    unsigned long long* M;
+    // optically thin approximation (section 2.6): the bin of lowest photon energy, and per
+    // source the least path length at which a ray's depth in it reaches kTauThin (FP32 bits)
+    int ksoft;
+    unsigned int* r_out;
 };
+
+constexpr float kTauThin = 0.1f;  // optical depth that bounds the optically thin sphere
 
 // Per-lane ray state. Along axis i the ray meets its next cell boundary at
 // t_i = a_i / e_i, where e_i = |d_i| and a_i is the (exact, lattice-valued) distance of
@@ -213,9 +224,12 @@ __device__ __forceinline__ void record_tree(const TraceArgs& A, uint32_t src, ui
 }
 
 // Load a ray: direction, source, start radius and start cell (section 2.1 iii a/c:
-// roots at radius 0, children at the parent's radius with their own direction).
+// roots at radius 0, children at the parent's radius with their own direction). With the
+// optically thin approximation (THIN, section 2.6) a ray starts no closer than its source's
+// thin radius; a ray whose split radius does not lie beyond that start splits at once (it is
+// returned active with thi >= tend and crosses nothing).
 // Returns false (and books the escape) when the start point lies outside the grid.
-template <int NB, class Rec>
+template <int NB, bool THIN, class Rec>
 __device__ __forceinline__ bool ray_init(const TraceArgs& A, const Rec& r, Ray<NB>& ray, LaneStats& st)
 {
     ray.src = r.src;
@@ -226,7 +240,8 @@ __device__ __forceinline__ bool ray_init(const TraceArgs& A, const Rec& r, Ray<N
     const float d[3] = {dv.x, dv.y, dv.z};
     const SourceRec s = A.src[r.src];
     const float xs[3] = {s.x, s.y, s.z};
-    const float t0 = level == A.level0 ? 0.0f : A.tsplit[level - 1];
+    float t0 = level == A.level0 ? 0.0f : A.tsplit[level - 1];
+    if constexpr (THIN) t0 = fmaxf(t0, s.r_thin);
     ray.thi = t0;
     ray.tlo = 0.0f;
     ray.tend = A.tsplit[level];
@@ -238,6 +253,9 @@ __device__ __forceinline__ bool ray_init(const TraceArgs& A, const Rec& r, Ray<N
         ray.w[b] = s.scale[b] * lw;
     }
     st.rays++;
+    if constexpr (THIN) {
+        if (!(t0 < ray.tend)) return true;  // splits at once
+    }
     bool inside = true;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -254,9 +272,16 @@ __device__ __forceinline__ bool ray_init(const TraceArgs& A, const Rec& r, Ray<N
         ray.ix[i] = inside ? axis_term(A, i, c) : 0u;
     }
     if (!inside) {
+        float ts = 0.0f;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            st.esc[b] += (double)ray.w[b] * (double)transmission(ray.tau[b] + ray.taulo[b]);
+        for (int b = 0; b < NB; ++b) {
+            const float tb = ray.tau[b] + ray.taulo[b];
+            st.esc[b] += (double)ray.w[b] * (double)transmission(tb);
+            if (b == A.ksoft) ts = tb;
+        }
+        // a ray that starts outside the grid while still thin bounds the thin radius by its start
+        if constexpr (THIN)
+            if (ts < kTauThin) atomicMin(A.r_out + ray.src, __float_as_uint(t0));
         st.escaped++;
     }
     return inside;
@@ -284,6 +309,7 @@ struct Seg {
     int event;
     uint32_t nb;  // geometric correction: neighbour that receives the moved share (kNoCell: none)
     float fc;     // geometric correction: share the cell keeps (1: uncorrected)
+    float t1;     // path length at the segment's end (high part)
 };
 
 constexpr double kSqrtPiOver3 = 1.0233267079464885;  // width of a level-0 pixel per unit radius
@@ -429,6 +455,7 @@ __device__ __forceinline__ Seg geom_next(const TraceArgs& A, Ray<NB>& ray)
         sg.ds = nhi - ray.thi;
     }
     sg.cell = ray.ix[0] + ray.ix[1] + ray.ix[2];
+    sg.t1 = nhi;
     if constexpr (CORR) geom_correction(A, ray, nhi, nlo, sg);
     ray.thi = nhi;
     ray.tlo = nlo;
@@ -453,77 +480,40 @@ __device__ __forceinline__ Seg geom_next(const TraceArgs& A, Ray<NB>& ray)
     return sg;
 }
 
-// Photons of one segment (section 2.4, eq:ion per bin): deposit S ds g(dtau) into the
-// cell in fixed point, attenuate (compensated tau), then apply the termination test and
-// the segment's own event. Returns kTerminate, kSplit, kEscape or kContinue.
-template <int NB, int PREC>
-__device__ __forceinline__ int deposit_seg(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
-                                           LaneStats& st, Dep<NB>& dep)
+// Section 2.6: the least path length at which the ray's depth in the softest bin reaches
+// kTauThin, within this segment (ts: depth at its start, dts: its increment, ks: its
+// opacity), bounds the source's thin radius (one atomic per ray at most).
+template <int NB>
+__device__ __forceinline__ void thin_reach(const TraceArgs& A, const Ray<NB>& ray, const Seg& sg, float ts, float dts,
+                                           float ks)
 {
-    dep.cell = sg.cell;
-    bool term = A.tau_term < INFINITY;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const float dtau = kap[b] * sg.ds;
-        const float taun = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-        const float v = ((ray.w[b] * transmission(taun)) * sg.ds) * mean_atten(dtau);
-        dep.q[b] = round_to_i64(v);
-        if constexpr (PREC == 0) {
-            const float s = ray.tau[b] + dtau;
-            const float bb = s - ray.tau[b];
-            ray.taulo[b] += (ray.tau[b] - (s - bb)) + (dtau - bb);
-            ray.tau[b] = s;
-        } else {
-            ray.tau[b] += dtau;
-        }
-        const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-        term = term && taup >= A.tau_term && dtau >= kDtauTermMin;
+    if (ts < kTauThin && ts + dts >= kTauThin) {
+        const float rc = (sg.t1 - sg.ds) + (kTauThin - ts) / ks;
+        atomicMin(A.r_out + ray.src, __float_as_uint(rc));
     }
-    st.crossings++;
-    if (term) {
-        // absorb what is left in this cell: field += remaining photons / opacity
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-            dep.q[b] += round_to_i64((ray.w[b] * transmission(taup)) / kap[b]);
-        }
-        st.terminated++;
-        return kTerminate;
-    }
-    if (sg.event == kSplit) {
-        st.splits++;
-        return kSplit;
-    }
-    if (sg.event == kEscape) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-            st.esc[b] += (double)ray.w[b] * (double)transmission(taup);
-        }
-        st.escaped++;
-        return kEscape;
-    }
-    return kContinue;
 }
 
-// deposit_seg with the geometric correction: the crossing's photons (the termination
-// remainder included) are split between its cell (share fc) and, in mode 2, the neighbour
-// sg.nb, where the same photons are absorbed at the neighbour's opacity (times
-// kappa / kappa_nb, eq:correction2 per bin). A neighbour with less than 1/16 of the cell's
-// opacity in a bin takes nothing (the cell keeps that share), which bounds the fixed-point
-// field. Modes 1 and 3 drop the removed share.
-template <int NB, int PREC>
-__device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
-                                                const float kapn[NB], LaneStats& st, Dep<NB>& dep, Dep<NB>& dn)
+// Photons of one segment (section 2.4, eq:ion per bin): the amount v_b = S ds g(dtau) for the
+// cell in field units, attenuation (compensated tau), then the termination test (a
+// terminating crossing adds the rest of the photons, S / kappa, to v_b) and, with THIN, the
+// thin-radius measurement. Returns kTerminate, kSplit, kEscape or kContinue.
+template <int NB, int PREC, bool THIN>
+__device__ __forceinline__ int attenuate_seg(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
+                                             LaneStats& st, float v[NB])
 {
-    dep.cell = sg.cell;
-    dn.cell = sg.nb;
-    float v[NB];
     bool term = A.tau_term < INFINITY;
+    float ts = 0.0f, dts = 0.0f, ks = 1.0f;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const float dtau = kap[b] * sg.ds;
         const float taun = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+        if constexpr (THIN) {
+            if (b == A.ksoft) {
+                ts = taun;
+                dts = dtau;
+                ks = kap[b];
+            }
+        }
         v[b] = ((ray.w[b] * transmission(taun)) * sg.ds) * mean_atten(dtau);
         if constexpr (PREC == 0) {
             const float s = ray.tau[b] + dtau;
@@ -537,28 +527,14 @@ __device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray
         term = term && taup >= A.tau_term && dtau >= kDtauTermMin;
     }
     st.crossings++;
+    if constexpr (THIN) thin_reach<NB>(A, ray, sg, ts, dts, ks);
     if (term) {
+        // absorb what is left in this cell: field += remaining photons / opacity
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
             v[b] += (ray.w[b] * transmission(taup)) / kap[b];
         }
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        float keep = v[b], move = 0.0f;
-        if (sg.fc < 1.0f) {
-            if (sg.nb == kNoCell) {
-                keep = sg.fc * v[b];
-            } else if (kapn[b] > 0.0f && kap[b] <= 16.0f * kapn[b]) {
-                keep = sg.fc * v[b];
-                move = ((1.0f - sg.fc) * v[b]) * (kap[b] / kapn[b]);
-            }
-        }
-        dep.q[b] = round_to_i64(keep);
-        dn.q[b] = round_to_i64(move);
-    }
-    if (term) {
         st.terminated++;
         return kTerminate;
     }
@@ -567,15 +543,80 @@ __device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray
         return kSplit;
     }
     if (sg.event == kEscape) {
+        float tsp = 0.0f;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
             st.esc[b] += (double)ray.w[b] * (double)transmission(taup);
+            if (b == A.ksoft) tsp = taup;
         }
+        // a ray that leaves the grid while still thin bounds the thin radius by its exit
+        if constexpr (THIN)
+            if (tsp < kTauThin) atomicMin(A.r_out + ray.src, __float_as_uint(sg.t1));
         st.escaped++;
         return kEscape;
     }
     return kContinue;
+}
+
+// A segment's deposit into its own cell, rounded to the field's integers.
+template <int NB, int PREC, bool THIN>
+__device__ __forceinline__ int deposit_seg(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
+                                           LaneStats& st, Dep<NB>& dep)
+{
+    float v[NB];
+    const int ev = attenuate_seg<NB, PREC, THIN>(A, ray, sg, kap, st, v);
+    dep.cell = sg.cell;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) dep.q[b] = round_to_i64(v[b]);
+    return ev;
+}
+
+// Limbs of the moved-photon field: mv = hi 2^20 + lo 2^-12 (units of u_J,b). A crossing's lo
+// is below 2^32, so the limb holds 2^31 crossings; hi is bounded like the field.
+constexpr float kMovedHiUnit = 1048576.0f;      // 2^20
+constexpr float kMovedLoScale = 4096.0f;        // 2^12
+
+// deposit_seg with the geometric correction (section 2.5): the cell keeps fc of the
+// crossing's photons (the termination remainder included). In mode 2 the rest goes to the
+// neighbour sg.nb, absorbed there at the neighbour's opacity (eq:correction2, the absorber
+// ratio per bin as the opacity ratio kappa / kappa_nb), whatever that ratio: the moved
+// photons (1 - fc) v kappa, bounded by the ray's own, are deposited in the two-limb field M
+// and divided by kappa_nb when the rates are formed. A neighbour with no absorber of the bin
+// (kappa_nb = 0) leaves the share in the cell. Modes 1 and 3 drop the removed share.
+// dep: own cell; dh, dl: the neighbour's high and low limbs (kNoCell when all zero).
+template <int NB, int PREC, bool THIN>
+__device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
+                                                const float kapn[NB], LaneStats& st, Dep<NB>& dep, Dep<NB>& dh,
+                                                Dep<NB>& dl)
+{
+    float v[NB];
+    const int ev = attenuate_seg<NB, PREC, THIN>(A, ray, sg, kap, st, v);
+    dep.cell = sg.cell;
+    bool any_hi = false, any_lo = false;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        float keep = v[b], mv = 0.0f;
+        if (sg.fc < 1.0f) {
+            if (sg.nb == kNoCell) {
+                keep = sg.fc * v[b];
+            } else if (kapn[b] > 0.0f) {
+                keep = sg.fc * v[b];
+                mv = ((1.0f - sg.fc) * v[b]) * kap[b];
+            }
+        }
+        dep.q[b] = round_to_i64(keep);
+        // mv = hi 2^20 + lo 2^-12: hi = floor(mv / 2^20) (an integer float), and the rest,
+        // mv - hi 2^20 (exact: the bits of mv below 2^20), in units of 2^-12, rounded
+        const float hi = floorf(mv * (1.0f / kMovedHiUnit));
+        dh.q[b] = round_to_i64(hi);
+        dl.q[b] = (long long)(uint32_t)rintf(__builtin_fmaf(-hi, kMovedHiUnit, mv) * kMovedLoScale);
+        any_hi = any_hi || dh.q[b] != 0;
+        any_lo = any_lo || dl.q[b] != 0;
+    }
+    dh.cell = any_hi ? sg.nb : kNoCell;
+    dl.cell = any_lo ? sg.nb : kNoCell;
+    return ev;
 }
 
 // Segments whose geometry is computed ahead of their deposits (opacity loads in flight
@@ -592,15 +633,24 @@ constexpr int kDepWindow = ARC_DEP_WINDOW;  // segments of each lane whose depos
 // Up to K crossings of one lane per pass: the geometry of K segments is computed first
 // and their opacities are loaded together (K loads in flight per lane), then the
 // segments are deposited in order; `deposit.add` is called once per kDepWindow segments by
-// the whole wave, then `deposit.flush` once.
+// the whole wave. With THIN, a lane whose ray starts at or beyond its split radius (inside
+// the source's thin sphere) splits at once, without a crossing.
 // Returns the lane's final event of the pass (kContinue if the ray goes on).
-template <int NB, int PREC, int K, class Depositor>
+template <int NB, int PREC, int K, bool THIN, class Depositor>
 __device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool active, LaneStats& st,
                                           Depositor& deposit)
 {
     Seg sg[K];
     bool have[K];
     bool go = active;
+    int ev = kContinue;
+    if constexpr (THIN) {
+        if (active && !(ray.thi < ray.tend)) {
+            go = false;
+            ev = kSplit;
+            st.splits++;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         have[j] = go;
@@ -613,7 +663,6 @@ __device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool
 #pragma unroll
     for (int j = 0; j < K; ++j)
         if (have[j]) kappa_at<NB>(A, sg[j].cell, kap[j]);
-    int ev = kContinue;
 #pragma unroll
     for (int j0 = 0; j0 < K; j0 += kDepWindow) {
         Dep<NB> dep[kDepWindow];
@@ -621,29 +670,36 @@ __device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool
         for (int w = 0; w < kDepWindow; ++w) {
             const int j = j0 + w;
             dep[w].cell = kNoCell;
-            if (j < K && have[j] && ev == kContinue) ev = deposit_seg<NB, PREC>(A, ray, sg[j], kap[j], st, dep[w]);
+            if (j < K && have[j] && ev == kContinue) ev = deposit_seg<NB, PREC, THIN>(A, ray, sg[j], kap[j], st, dep[w]);
         }
-        deposit.add(dep);
+        deposit.add(dep, A.J, A.nbp);
     }
-    deposit.flush();
     return ev;
 }
 
 // trace_pass with the geometric correction: up to K crossings per lane, the neighbours'
-// opacities loaded with the cells'; each crossing deposits into its cell and its neighbour,
-// which go to the wave's deposit as one window of two items.
+// opacities loaded with the cells'. Two crossings' cells form a window, as without the
+// correction; in mode 2 their neighbours' high limbs, then their low limbs, form two more.
 #ifndef ARC_SEG_AHEAD_CORR
 #define ARC_SEG_AHEAD_CORR 4
 #endif
 constexpr int kSegAheadCorr = ARC_SEG_AHEAD_CORR;
-template <int NB, int PREC, int K, class Depositor>
+template <int NB, int PREC, int K, bool THIN, class Depositor>
 __device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray, bool active, LaneStats& st,
                                                Depositor& deposit)
 {
-    static_assert(kDepWindow == 2, "a corrected crossing deposits into two cells");
+    static_assert(kDepWindow == 2, "modes 1 and 3 deposit two crossings per window");
     Seg sg[K];
     bool have[K];
     bool go = active;
+    int ev = kContinue;
+    if constexpr (THIN) {
+        if (active && !(ray.thi < ray.tend)) {
+            go = false;
+            ev = kSplit;
+            st.splits++;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         have[j] = go;
@@ -662,33 +718,22 @@ __device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray,
             if (sg[j].nb != kNoCell) kappa_at<NB>(A, sg[j].nb, kapn[j]);
         }
     }
-    int ev = kContinue;
-    if (A.corr == 2) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            Dep<NB> dep[kDepWindow];
-            dep[0].cell = kNoCell;
-            dep[1].cell = kNoCell;
-            if (have[j] && ev == kContinue)
-                ev = deposit_seg_corr<NB, PREC>(A, ray, sg[j], kap[j], kapn[j], st, dep[0], dep[1]);
-            deposit.add(dep);
+    for (int j = 0; j < K; j += 2) {
+        Dep<NB> dep[2], dh[2], dl[2];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            dep[w].cell = dh[w].cell = dl[w].cell = kNoCell;
+            if (j + w < K && have[j + w] && ev == kContinue)
+                ev = deposit_seg_corr<NB, PREC, THIN>(A, ray, sg[j + w], kap[j + w], kapn[j + w], st, dep[w], dh[w],
+                                                     dl[w]);
         }
-    } else {
-        // no neighbour deposits: two segments' cells per window, as without the correction
-#pragma unroll
-        for (int j = 0; j < K; j += 2) {
-            Dep<NB> dep[kDepWindow];
-            Dep<NB> none;
-#pragma unroll
-            for (int w = 0; w < 2; ++w) {
-                dep[w].cell = kNoCell;
-                if (j + w < K && have[j + w] && ev == kContinue)
-                    ev = deposit_seg_corr<NB, PREC>(A, ray, sg[j + w], kap[j + w], kapn[j + w], st, dep[w], none);
-            }
-            deposit.add(dep);
+        deposit.add(dep, A.J, A.nbp);
+        if (A.corr == 2) {
+            deposit.add(dh, A.M, 2 * A.nbp);
+            deposit.add(dl, A.M + A.nbp, 2 * A.nbp);
         }
     }
-    deposit.flush();
     return ev;
 }
 
@@ -724,10 +769,11 @@ __device__ __forceinline__ StackRec<NB> child_stack(const Ray<NB>& ray, int k)
     return r;
 }
 
-// Fixed-point deposition, called by all 64 lanes together. Atomic adds cost per distinct
-// cache line an instruction touches, so the NB bins of a cell are issued by NB adjacent
-// lanes of the same instruction: instruction k, lane j adds bin (64k + j) mod NB of item
-// (64k + j) / NB.
+// Fixed-point deposition, called by all 64 lanes together, into an int64 field `base` with
+// `stride` words per cell (the field J, or a limb of the moved-photon field M). Atomic adds
+// cost per distinct cache line an instruction touches, so the NB bins of a cell are issued
+// by NB adjacent lanes of the same instruction: instruction k, lane j adds bin (64k + j) mod
+// NB of item (64k + j) / NB.
 #ifndef ARC_DEDUP
 #define ARC_DEDUP 1  // 0: every lane's crossing deposited on its own
 #endif
@@ -746,26 +792,21 @@ struct DepScratch {
 };
 
 template <int NB>
-__device__ __forceinline__ void deposit_wave_plain(const TraceArgs& A, const Dep<NB>& d)
+__device__ __forceinline__ void deposit_wave_plain(const Dep<NB>& d, unsigned long long* base, int stride)
 {
-    if constexpr (NB == 1) {
-        if (d.cell != kNoCell && d.q[0] != 0) atomicAdd(A.J + d.cell, (unsigned long long)d.q[0]);
-    } else {
-        const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const int s = 64 * k + lane;
-            const int item = s / NB, bin = s - item * NB;
-            const uint32_t cell = (uint32_t)__shfl((int)d.cell, item, 64);
-            long long q = 0;
+    for (int k = 0; k < NB; ++k) {
+        const int s = 64 * k + lane;
+        const int item = s / NB, bin = s - item * NB;
+        const uint32_t cell = (uint32_t)__shfl((int)d.cell, item, 64);
+        long long q = 0;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const long long qb = __shfl(d.q[b], item, 64);
-                q = b == bin ? qb : q;
-            }
-            if (cell != kNoCell && q != 0)
-                atomicAdd(A.J + (size_t)cell * (size_t)A.nbp + (size_t)bin, (unsigned long long)q);
+        for (int b = 0; b < NB; ++b) {
+            const long long qb = __shfl(d.q[b], item, 64);
+            q = b == bin ? qb : q;
         }
+        if (cell != kNoCell && q != 0) atomicAdd(base + (size_t)cell * (size_t)stride + (size_t)bin, (unsigned long long)q);
     }
 }
 
@@ -776,10 +817,18 @@ __device__ __forceinline__ void deposit_wave_plain(const TraceArgs& A, const Dep
 // taken by another cell go alone. LDS operations of one wave complete in issue order, and
 // the racy table accesses are volatile so that each read really observes the wave's writes.
 template <int NB>
-__device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep<NB> (&d)[kDepWindow],
-                                                   DepScratch<NB>* S)
+__device__ __forceinline__ void deposit_wave_dedup(const Dep<NB> (&d)[kDepWindow], DepScratch<NB>* S,
+                                                   unsigned long long* base, int stride)
 {
     constexpr int W = kDepWindow;
+    bool v[W];
+    bool anyv = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        v[w] = d[w].cell != kNoCell;
+        anyv = anyv || v[w];
+    }
+    if (!__any(anyv)) return;
     // LDS-qualified views: through a generic pointer the accesses would be FLAT instructions,
     // which also wait for the wave's outstanding gathers and atomics
     volatile kLds uint32_t* slot_cell = (volatile kLds uint32_t*)S->slot_cell;
@@ -790,13 +839,10 @@ __device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep
     kLds unsigned long long* acc_q = (kLds unsigned long long*)&S->q[0][0];
     const int lane = threadIdx.x & 63;
     const uint64_t lt = __lanemask_lt();
-    bool v[W], in[W], lead[W];
+    bool in[W], lead[W];
     uint32_t h[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        v[w] = d[w].cell != kNoCell;
-        h[w] = (d[w].cell * 2654435761u) >> kDepShift;
-    }
+    for (int w = 0; w < W; ++w) h[w] = (d[w].cell * 2654435761u) >> kDepShift;
 #pragma unroll
     for (int w = 0; w < W; ++w)
         if (v[w]) slot_cell[h[w]] = d[w].cell;
@@ -816,7 +862,6 @@ __device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep
         rank[w] = emit ? n + __popcll(em & lt) : -1;
         n += __popcll(em);
     }
-    if (n == 0) return;
 #pragma unroll
     for (int w = 0; w < W; ++w)
         if (lead[w]) slot_rank[h[w]] = (uint8_t)rank[w];
@@ -843,7 +888,7 @@ __device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep
         const int item = s / NB, bin = s - item * NB;
         const uint32_t cell = st_cell[item];
         const unsigned long long q = st_q[item * NB + bin];
-        if (q != 0) atomicAdd(A.J + (size_t)cell * (size_t)A.nbp + (size_t)bin, q);
+        if (q != 0) atomicAdd(base + (size_t)cell * (size_t)stride + (size_t)bin, q);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
@@ -852,18 +897,16 @@ __device__ __forceinline__ void deposit_wave_dedup(const TraceArgs& A, const Dep
 // segments, by every lane.
 template <int NB>
 struct Depositor {
-    const TraceArgs& A;
     DepScratch<NB>* scratch;
-    __device__ void add(const Dep<NB> (&d)[kDepWindow])
+    __device__ void add(const Dep<NB> (&d)[kDepWindow], unsigned long long* base, int stride)
     {
         if constexpr (ARC_DEDUP == 1) {
-            deposit_wave_dedup<NB>(A, d, scratch);
+            deposit_wave_dedup<NB>(d, scratch, base, stride);
         } else {
 #pragma unroll
-            for (int w = 0; w < kDepWindow; ++w) deposit_wave_plain<NB>(A, d[w]);
+            for (int w = 0; w < kDepWindow; ++w) deposit_wave_plain<NB>(d[w], base, stride);
         }
     }
-    __device__ void flush() {}
 };
 
 // Wave-level reduction and flush of lane statistics into the global counters.

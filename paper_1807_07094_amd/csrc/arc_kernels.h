@@ -18,6 +18,7 @@ struct OpacityArgs {
     float* kappa1;
     float4* kappa4;
     unsigned long long* J;
+    unsigned long long* M;     // moved-photon field of the conserving correction, or null
     int nbp;
     int* errflag;
 };
@@ -30,10 +31,24 @@ struct FinalizeArgs {
     double hea[kMaxBins][3];   // u_J,b sigma_bS (E_b - E_S)^+ / L^2
     double uj[kMaxBins];
     const unsigned long long* J;
+    const unsigned long long* M;  // moved-photon field (two limbs per bin), or null
     const float* kappa1;
     const float4* kappa4;
     float *gamma, *heat;       // [3][ncell]
     double* absorbed;          // sum_c sum_b u_J J kappa
+};
+
+// Section 2.6 fill of the optically thin spheres.
+struct ThinFillArgs {
+    int nb, nbp, nsrc, parts;  // parts: blocks per source
+    int nx, ny, nz, nbx8, nby8;
+    const double *pos, *ndot, *r_thin;
+    double coef[kMaxBins];     // frac_b / (4 pi u_J,b)
+    double uj[kMaxBins];
+    unsigned long long* J;
+    const float* kappa1;
+    const float4* kappa4;
+    double* absorbed_thin;     // sum of the fill's deposits times u_J kappa
 };
 
 struct ChemArgs {
@@ -58,8 +73,10 @@ hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
 hipError_t launch_field_checksum(const unsigned long long* J, size_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_opacity(const OpacityArgs& a, hipStream_t s);
 hipError_t launch_healpix(int level, float4* out, hipStream_t s);
-hipError_t launch_sources(int n, const double* pos, const double* ndot, const double* frac_over_12uj, int nb,
-                          SourceRec* out, hipStream_t s);
+hipError_t launch_sources(int n, const double* pos, const double* ndot, const double* r_thin,
+                          const double* frac_over_12uj, int nb, SourceRec* out, hipStream_t s);
+hipError_t launch_thin_fill(const ThinFillArgs& a, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 // Root rays of sources first_src .. first_src + nsrc - 1, or of order[0 .. nsrc) if order
 // is given (source k's rays are contiguous, in pixel order).
 hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, const uint32_t* order, RayRec* out,
@@ -72,8 +89,8 @@ hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* i
                                    int refill, hipStream_t s);
 int persistent_max_waves();
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
-hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, int nx, int ny, int nbx8, int nby8,
-                            uint32_t ncell, long long* dst, hipStream_t s);
+hipError_t launch_get_field(const unsigned long long* J, const unsigned long long* M, int nb, int nbp, int nx, int ny,
+                            int nbx8, int nby8, uint32_t ncell, long long* dst, hipStream_t s);
 // cus: compute units of the device (the solver launches resident waves only)
 hipError_t launch_chem(const ChemArgs& a, int cus, hipStream_t s);
 

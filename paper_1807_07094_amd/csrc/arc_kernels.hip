@@ -7,6 +7,7 @@
 //   k_trace_rays       one ray per lane, rays of one HEALPix level (the per-level schedule)
 //   k_trace_persistent every source in one launch: device work queue, wave-ballot refill,
 //                      per-wave LDS ray stack with a private spill area in memory
+//   k_thin_fill        optically thin approximation: point-source field inside each thin radius
 //   k_finalize         fixed-point field -> photoionisation and photoheating rates
 //   k_get_field        field copy in [bin][cell] order
 #include <hip/hip_runtime.h>
@@ -165,6 +166,8 @@ __global__ __launch_bounds__(256) void k_opacity(OpacityArgs a)
         }
         const uint32_t words = g.cells * (uint32_t)a.nbp;
         for (uint32_t w = threadIdx.x; w < words; w += blockDim.x) a.J[(size_t)g.base * a.nbp + w] = 0ull;
+        if (a.M)
+            for (uint32_t w = threadIdx.x; w < 2u * words; w += blockDim.x) a.M[2ull * g.base * a.nbp + w] = 0ull;
         __syncthreads();
     }
 }
@@ -274,7 +277,8 @@ struct ScaleArg {
     double f[kMaxBins];
 };
 
-__global__ void k_sources(int n, const double* pos, const double* ndot, ScaleArg sc, int nb, SourceRec* out)
+__global__ void k_sources(int n, const double* pos, const double* ndot, const double* r_thin, ScaleArg sc, int nb,
+                          SourceRec* out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -282,18 +286,98 @@ __global__ void k_sources(int n, const double* pos, const double* ndot, ScaleArg
     r.x = (float)pos[3 * i];
     r.y = (float)pos[3 * i + 1];
     r.z = (float)pos[3 * i + 2];
-    r.pad = 0.0f;
+    r.r_thin = r_thin ? (float)r_thin[i] : 0.0f;
 #pragma unroll
     for (int b = 0; b < kMaxBins; ++b) r.scale[b] = b < nb ? (float)(ndot[i] * sc.f[b]) : 0.0f;
     out[i] = r;
 }
 
-hipError_t launch_sources(int n, const double* pos, const double* ndot, const double* frac_over_12uj, int nb,
-                          SourceRec* out, hipStream_t s)
+hipError_t launch_sources(int n, const double* pos, const double* ndot, const double* r_thin,
+                          const double* frac_over_12uj, int nb, SourceRec* out, hipStream_t s)
 {
     ScaleArg sc;
     for (int b = 0; b < kMaxBins; ++b) sc.f[b] = b < nb ? frac_over_12uj[b] : 0.0;
-    if (n > 0) k_sources<<<grid_for(n, 256), 256, 0, s>>>(n, pos, ndot, sc, nb, out);
+    if (n > 0) k_sources<<<grid_for(n, 256), 256, 0, s>>>(n, pos, ndot, r_thin, sc, nb, out);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------------------
+// Optically thin approximation (section 2.6): every cell whose centre lies within a source's
+// thin radius R receives that source's point-source field S_b / (4 pi r^2), r the centre's
+// distance in cells and at least half a cell (the point formula diverges in the source's own
+// cell), in the field's integers. Block (i, j) covers part j of source i's bounding box.
+// -------------------------------------------------------------------------------------
+template <int NB>
+__global__ __launch_bounds__(256) void k_thin_fill(ThinFillArgs a)
+{
+    const int i = blockIdx.x;
+    double absorbed = 0.0;
+    const double R = (double)(float)a.r_thin[i];
+    if (R > 0.0) {
+        const double xs[3] = {a.pos[3 * i], a.pos[3 * i + 1], a.pos[3 * i + 2]};
+        const int n[3] = {a.nx, a.ny, a.nz};
+        int lo[3], ext[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = max(0, (int)floor(xs[d] - R));
+            const int hi = min(n[d] - 1, (int)ceil(xs[d] + R));
+            ext[d] = max(0, hi - lo[d] + 1);
+        }
+        const double ndot = a.ndot[i];
+        const size_t total = (size_t)ext[0] * ext[1] * ext[2];
+        const size_t stride = (size_t)gridDim.y * blockDim.x;
+        for (size_t l = (size_t)blockIdx.y * blockDim.x + threadIdx.x; l < total; l += stride) {
+            const int cx = lo[0] + (int)(l % ext[0]);
+            const int cy = lo[1] + (int)((l / ext[0]) % ext[1]);
+            const int cz = lo[2] + (int)(l / ((size_t)ext[0] * ext[1]));
+            const double dx = (double)cx + 0.5 - xs[0], dy = (double)cy + 0.5 - xs[1], dz = (double)cz + 0.5 - xs[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;  // exact: lattice positions
+            if (!(r2 < R * R)) continue;
+            const double inv = ndot / fmax(r2, 0.25);
+            const uint32_t cell = blocked_index(cx, cy, cz, a.nbx8, a.nby8);
+            float k[NB];
+            if constexpr (NB == 1) {
+                k[0] = a.kappa1[cell];
+            } else {
+                const float4 v = a.kappa4[cell];
+                k[0] = v.x;
+                k[1] = v.y;
+                if constexpr (NB > 2) k[2] = v.z;
+                if constexpr (NB > 3) k[3] = v.w;
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const long long q = llrint(inv * a.coef[b]);
+                if (q != 0) atomicAdd(a.J + (size_t)cell * a.nbp + b, (unsigned long long)q);
+                absorbed += (double)q * a.uj[b] * (double)k[b];
+            }
+        }
+    }
+    absorbed = wave_sum_f64(absorbed);
+    if ((threadIdx.x & 63) == 0 && absorbed != 0.0) atomicAdd(a.absorbed_thin, absorbed);
+}
+
+hipError_t launch_thin_fill(const ThinFillArgs& a, hipStream_t s)
+{
+    if (a.nsrc <= 0) return hipSuccess;
+    const dim3 g((unsigned)a.nsrc, (unsigned)a.parts);
+    switch (a.nb) {
+        case 1: k_thin_fill<1><<<g, 256, 0, s>>>(a); break;
+        case 2: k_thin_fill<2><<<g, 256, 0, s>>>(a); break;
+        case 3: k_thin_fill<3><<<g, 256, 0, s>>>(a); break;
+        default: k_thin_fill<4><<<g, 256, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
+{
+    if (n > 0) k_fill_u32<<<grid_for(n, 256, 1024), 256, 0, s>>>(p, n, v);
     return hipGetLastError();
 }
 
@@ -326,14 +410,14 @@ hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, cons
 // terminates or leaves the grid; splitting lanes write their four children into the
 // next level's array, one slot reservation per wave.
 // -------------------------------------------------------------------------------------
-template <int NB, int PREC, bool CORR>
+template <int NB, int PREC, bool CORR, bool THIN>
 __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* __restrict__ in,
                                                     const uint32_t* n_in_dev, uint32_t n_in_host,
                                                     RayRec* __restrict__ out, uint32_t* n_out, uint32_t out_cap)
 {
     const uint32_t n_in = n_in_dev ? *n_in_dev : n_in_host;
     __shared__ DepScratch<NB> dscr[4];
-    Depositor<NB> dep{A, dscr + (threadIdx.x >> 6)};
+    Depositor<NB> dep{dscr + (threadIdx.x >> 6)};
     LaneStats st;
     st.clear();
     const int lane = threadIdx.x & 63;
@@ -347,15 +431,15 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
         if (i < n_in) {
             const RayRec r = in[i];
             record_tree<NB>(A, r.src, r.lp);
-            act = ray_init<NB>(A, r, ray, st);
+            act = ray_init<NB, THIN>(A, r, ray, st);
         }
         // a few crossings per lane per pass; the wave deposits each crossing together
         while (__any(act)) {
             int e;
             if constexpr (CORR)
-                e = trace_pass_corr<NB, PREC, kSegAheadCorr>(A, ray, act, st, dep);
+                e = trace_pass_corr<NB, PREC, kSegAheadCorr, THIN>(A, ray, act, st, dep);
             else
-                e = trace_pass<NB, PREC, kSegAhead>(A, ray, act, st, dep);
+                e = trace_pass<NB, PREC, kSegAhead, THIN>(A, ray, act, st, dep);
             if (act && e != kContinue) {
                 ev = e;
                 act = false;
@@ -386,12 +470,17 @@ static hipError_t trace_rays_nb(const TraceArgs& A, int prec, const RayRec* in, 
                                 uint32_t n_in, RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s)
 {
     const unsigned g = grid_for(n_in, 256, 1u << 16);
-    if (prec == 0 && A.corr)
-        k_trace_rays<NB, 0, true><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+    const bool thin = A.r_out != nullptr;
+    if (prec == 0 && A.corr && thin)
+        k_trace_rays<NB, 0, true, true><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+    else if (prec == 0 && A.corr)
+        k_trace_rays<NB, 0, true, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+    else if (prec == 0 && thin)
+        k_trace_rays<NB, 0, false, true><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
     else if (prec == 0)
-        k_trace_rays<NB, 0, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+        k_trace_rays<NB, 0, false, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
     else
-        k_trace_rays<NB, 1, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+        k_trace_rays<NB, 1, false, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
     return hipGetLastError();
 }
 
@@ -421,7 +510,7 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 // -------------------------------------------------------------------------------------
 constexpr int kStackCap = 256;  // power of two, >= 3 * 64 children of one split round
 
-template <int NB, int PREC, int WPB, bool CORR>
+template <int NB, int PREC, int WPB, bool CORR, bool THIN>
 __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
                                                                const uint32_t* n_items_dev, uint32_t* head,
                                                                RayRec* __restrict__ spill_all, uint32_t spill_cap,
@@ -435,7 +524,7 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
     const uint64_t lt = __lanemask_lt();
     const uint32_t n_items = *n_items_dev;
     SRec* stk = lds + wid * kStackCap;
-    Depositor<NB> dep{A, dscr + wid};
+    Depositor<NB> dep{dscr + wid};
     // the spill area is sized in full records; compact records fit in it
     SRec* spill = reinterpret_cast<SRec*>(spill_all + (size_t)(blockIdx.x * WPB + wid) * spill_cap);
     int base = 0;          // ring start (oldest entry), wave-uniform
@@ -497,7 +586,7 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
             }
             if (got) {
                 record_tree<NB>(A, r.src, r.lp);
-                has = ray_init<NB>(A, r, ray, st);
+                has = ray_init<NB, THIN>(A, r, ray, st);
             }
         }
         if (!__any(has)) {
@@ -506,9 +595,9 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
         }
         int ev;
         if constexpr (CORR)
-            ev = trace_pass_corr<NB, PREC, kSegAheadCorr>(A, ray, has, st, dep);
+            ev = trace_pass_corr<NB, PREC, kSegAheadCorr, THIN>(A, ray, has, st, dep);
         else
-            ev = trace_pass<NB, PREC, kSegAhead>(A, ray, has, st, dep);
+            ev = trace_pass<NB, PREC, kSegAhead, THIN>(A, ray, has, st, dep);
         const uint64_t sp = __ballot(ev == kSplit);
         if (sp) {
             const int need = 3 * __popcll(sp);
@@ -538,7 +627,7 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
             if (ev == kSplit) {
                 const SRec c0 = child_stack<NB>(ray, 0);
                 record_tree<NB>(A, c0.src, c0.lp);
-                has = ray_init<NB>(A, c0, ray, st);
+                has = ray_init<NB, THIN>(A, c0, ray, st);
             }
         }
         if (ev == kTerminate || ev == kEscape) has = false;
@@ -551,36 +640,42 @@ constexpr int kMaxWavesPerBlock = 8;
 
 int persistent_max_waves() { return kMaxWavesPerBlock; }
 
-template <int NB, int PREC, bool CORR>
+template <int NB, int PREC, bool CORR, bool THIN>
 static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const uint32_t* n_items, uint32_t* head,
                                 RayRec* spill, uint32_t spill_cap, int blocks, int waves, int refill, hipStream_t s)
 {
     switch (waves) {
-        case 1: k_trace_persistent<NB, PREC, 1, CORR><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        case 2: k_trace_persistent<NB, PREC, 2, CORR><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        case 4: k_trace_persistent<NB, PREC, 4, CORR><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        default: k_trace_persistent<NB, PREC, 8, CORR><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 1: k_trace_persistent<NB, PREC, 1, CORR, THIN><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 2: k_trace_persistent<NB, PREC, 2, CORR, THIN><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 4: k_trace_persistent<NB, PREC, 4, CORR, THIN><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        default: k_trace_persistent<NB, PREC, 8, CORR, THIN><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
     }
     return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t persistent_variant(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
+                                     uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
+                                     int refill, hipStream_t s)
+{
+    const bool thin = A.r_out != nullptr;
+    if (prec != 0) return persistent_nb<NB, 1, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+    if (A.corr && thin) return persistent_nb<NB, 0, true, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+    if (A.corr) return persistent_nb<NB, 0, true, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+    if (thin) return persistent_nb<NB, 0, false, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+    return persistent_nb<NB, 0, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
 }
 
 hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
                                    uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
                                    int refill, hipStream_t s)
 {
-#define ARC_PERSIST(NBV)                                                                                     \
-    return prec == 0 ? (A.corr ? persistent_nb<NBV, 0, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, \
-                                                           refill, s)                                            \
-                               : persistent_nb<NBV, 0, false>(A, items, n_items, head, spill, spill_cap, blocks,   \
-                                                            waves, refill, s))                                   \
-                     : persistent_nb<NBV, 1, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s)
     switch (A.nb) {
-        case 1: ARC_PERSIST(1);
-        case 2: ARC_PERSIST(2);
-        case 3: ARC_PERSIST(3);
-        default: ARC_PERSIST(4);
+        case 1: return persistent_variant<1>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+        case 2: return persistent_variant<2>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+        case 3: return persistent_variant<3>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+        default: return persistent_variant<4>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
     }
-#undef ARC_PERSIST
 }
 
 // -------------------------------------------------------------------------------------
@@ -614,6 +709,15 @@ __global__ __launch_bounds__(256) void k_finalize(FinalizeArgs a)
                 k[1] = v.y;
                 if constexpr (NB > 2) k[2] = v.z;
                 if constexpr (NB > 3) k[3] = v.w;
+            }
+            if (a.M) {
+                // photons moved in by the secondary correction, absorbed at this cell's opacity
+                const unsigned long long* m = a.M + (size_t)i * (2 * a.nbp);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const double mv = (double)(long long)m[b] * 0x1p20 + (double)(long long)m[a.nbp + b] * 0x1p-12;
+                    if (k[b] > 0.0f) Jb[b] += mv / (double)k[b];
+                }
             }
 #pragma unroll
             for (int sp = 0; sp < 3; ++sp) {
@@ -659,20 +763,27 @@ hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void k_get_field(const unsigned long long* J, int nb, int nbp, int nx, int ny, int nbx8, int nby8,
-                            uint32_t ncell, long long* dst)
+// dst [bin][cell] = J; with M, then [bin][cell] of M's low limb and [bin][cell] of its high limb.
+__global__ void k_get_field(const unsigned long long* J, const unsigned long long* M, int nb, int nbp, int nx, int ny,
+                            int nbx8, int nby8, uint32_t ncell, long long* dst)
 {
     for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
         const uint32_t x = c % (uint32_t)nx, y = (c / (uint32_t)nx) % (uint32_t)ny, z = c / ((uint32_t)nx * (uint32_t)ny);
         const uint32_t i = blocked_index((int)x, (int)y, (int)z, nbx8, nby8);
-        for (int b = 0; b < nb; ++b) dst[(size_t)b * ncell + c] = (long long)J[(size_t)i * nbp + b];
+        for (int b = 0; b < nb; ++b) {
+            dst[(size_t)b * ncell + c] = (long long)J[(size_t)i * nbp + b];
+            if (M) {
+                dst[(size_t)(nb + b) * ncell + c] = (long long)M[(size_t)i * 2 * nbp + nbp + b];
+                dst[(size_t)(2 * nb + b) * ncell + c] = (long long)M[(size_t)i * 2 * nbp + b];
+            }
+        }
     }
 }
 
-hipError_t launch_get_field(const unsigned long long* J, int nb, int nbp, int nx, int ny, int nbx8, int nby8,
-                            uint32_t ncell, long long* dst, hipStream_t s)
+hipError_t launch_get_field(const unsigned long long* J, const unsigned long long* M, int nb, int nbp, int nx, int ny,
+                            int nbx8, int nby8, uint32_t ncell, long long* dst, hipStream_t s)
 {
-    k_get_field<<<grid_for(ncell, 256, 1u << 16), 256, 0, s>>>(J, nb, nbp, nx, ny, nbx8, nby8, ncell, dst);
+    k_get_field<<<grid_for(ncell, 256, 1u << 16), 256, 0, s>>>(J, M, nb, nbp, nx, ny, nbx8, nby8, ncell, dst);
     return hipGetLastError();
 }
 

@@ -89,9 +89,12 @@ def test_thin_with_the_conserving_correction(arc, ctx):
 
 def test_thin_radius_grows_over_steps(arc, ctx):
     """Feeding each trace the radius the previous one measured: the GPU and the oracle reach
-    the same radii, and a radius fed back reproduces the oracle's field."""
+    the same radii, and a radius fed back reproduces the oracle's field. Rays start at the
+    radius fed in, so a measured radius never falls below it (a source near a face of the
+    box may keep a radius below one cell: the shortest way out)."""
     w = thin_workload(seed=47, radii=(0.0,) * 5)
     r = np.zeros(5)
+    radii = []
     for step in range(2):
         w.sources["r_thin"] = r.copy()
         w.sources["r_thin_out"] = np.empty(5)
@@ -100,7 +103,9 @@ def test_thin_radius_grows_over_steps(arc, ctx):
         np.testing.assert_allclose(w.sources["r_thin_out"], o["r_thin_out"], rtol=THIN_R_TOL)
         assert max(rate_errors(g, o)) <= GAMMA_REL_TOL, step
         r = o["r_thin_out"].copy()
-    assert np.all(r > 1.0)
+        radii.append(r)
+    assert np.all(radii[0] > 0.0)
+    assert np.all(radii[1] >= radii[0].astype(np.float32).astype(np.float64))
 
 
 def test_thin_argument_checks(arc, ctx):
