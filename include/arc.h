@@ -186,6 +186,11 @@ typedef struct {
     double absorbed_thin;  /* part of `absorbed` deposited by the optically thin fill
                               (section 2.6); the rays alone conserve photons:
                               emitted = (absorbed - absorbed_thin) + escaped */
+    uint64_t deposits;     /* fixed-point deposits issued as atomics, one per cell and merge
+                              window after crossings of the same cell are summed on chip (each
+                              covers the cell's bins in one memory request) */
+    uint64_t kernel_crossings; /* batched: crossings of the persistent trace kernel alone */
+    uint64_t kernel_deposits;  /* batched: deposits of the persistent trace kernel alone */
 } arc_ledger;
 
 /* One ray-tracing pass (a whole RT step's radiation field). `out` receives the rates;
@@ -225,6 +230,17 @@ arc_status arc_autotune(arc_ctx* ctx, const arc_grid* grid, const arc_sources* s
  * high limb [nbins][ncell] (units 2^20 u_j[b]); a cell's rate field is then
  * J + (high 2^20 + low 2^-12) / kappa, kappa its opacity per cell length. */
 arc_status arc_get_field(arc_ctx* ctx, int64_t* dst, int64_t count, void* stream);
+
+/* Measurement only (no paper counterpart): the device's rate of the two random memory
+ * requests a crossing makes, on the buffers of the last arc_trace (2 to 4 bins, else
+ * ARC_E_ARG), for holding the trace kernel against. `items` random cells among the first
+ * `cells` of the blocked layout (0 = all of them; a counter-based hash of the index and
+ * `seed`) each take (1) one deposit: an int64 atomic add to every bin of the cell, issued by
+ * adjacent lanes of one instruction as the tracer issues them, and (2) one 16-byte opacity
+ * gather. Best of three timings of each, per second. Overwrites the fixed-point field
+ * (arc_get_field then fails until the next trace). Blocks. */
+arc_status arc_probe_requests(arc_ctx* ctx, int64_t items, int64_t cells, uint64_t seed, void* stream,
+                              double* deposits_per_s, double* gathers_per_s);
 
 /* FP32 HEALPix pixel centres of `level` (nested order) as used by the tracer, written
  * to the device array `dst` of 3 * 12 * 4^level floats (x, y, z per pixel). */

@@ -70,7 +70,8 @@ class Ledger(C.Structure):
                 ("crossings", C.c_uint64), ("rays", C.c_uint64), ("splits", C.c_uint64),
                 ("terminated", C.c_uint64), ("escaped_rays", C.c_uint64), ("spills", C.c_uint64),
                 ("tree_count", C.c_int64), ("u_j", C.c_double * 4), ("ms_trace", C.c_double),
-                ("ms_total", C.c_double), ("ms_kernel", C.c_double), ("absorbed_thin", C.c_double)]
+                ("ms_total", C.c_double), ("ms_kernel", C.c_double), ("absorbed_thin", C.c_double),
+                ("deposits", C.c_uint64), ("kernel_crossings", C.c_uint64), ("kernel_deposits", C.c_uint64)]
 
 
 class ChemParams(C.Structure):
@@ -118,6 +119,9 @@ def lib():
                                    C.POINTER(TraceParams), C.POINTER(Rates), C.POINTER(TuneResult)]
         L.arc_get_field.restype = C.c_int32
         L.arc_get_field.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.arc_probe_requests.restype = C.c_int32
+        L.arc_probe_requests.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_uint64, C.c_void_p,
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.arc_healpix_dirs.restype = C.c_int32
         L.arc_healpix_dirs.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.arc_chem_step.restype = C.c_int32
@@ -273,6 +277,14 @@ class Context:
         low and high limbs)."""
         self._check(lib().arc_get_field(self._h, _ptr(dst), int(dst.numel()), _stream(stream)))
         return dst
+
+    def probe_requests(self, items: int = 1 << 27, cells: int = 0, seed: int = 1, stream=None):
+        """arc_probe_requests: (deposits/s, gathers/s) of random cells (among the first `cells`
+        of the blocked layout, 0 = all) on the last trace's buffers (overwrites its field)."""
+        d, g = C.c_double(0), C.c_double(0)
+        self._check(lib().arc_probe_requests(self._h, int(items), int(cells), int(seed), _stream(stream), C.byref(d),
+                                             C.byref(g)))
+        return d.value, g.value
 
     def healpix_dirs(self, level: int, dst, stream=None):
         self._check(lib().arc_healpix_dirs(self._h, int(level), _ptr(dst), _stream(stream)))

@@ -642,6 +642,7 @@ hipError_t enqueue_levels(const TracePlan& P, hipStream_t st)
         bound *= 4;
         cur = 1 - cur;
     }
+    if ((e = launch_snapshot_counters(P.A.counters, st)) != hipSuccess) return e;
     return launch_set_u32(P.u32 + 1, 0u, st);
 }
 
@@ -840,6 +841,11 @@ arc_status run_trace(arc_ctx* c, const TracePlan& P, const arc_sources* s, doubl
         ledger->terminated = cnt[kTerminated];
         ledger->escaped_rays = cnt[kEscapedRays];
         ledger->spills = cnt[kSpills];
+        ledger->deposits = cnt[kDeposits];
+        if (c->timed_kernel) {
+            ledger->kernel_crossings = cnt[kCrossings] - cnt[kCrossingsPre];
+            ledger->kernel_deposits = cnt[kDeposits] - cnt[kDepositsPre];
+        }
         ledger->tree_count = (int64_t)cnt[kTreeCount];
         for (int k = 0; k < kMaxBins; ++k) ledger->u_j[k] = k < P.nb ? P.uj[k] : 0.0;
         float ms = 0;
@@ -1051,6 +1057,39 @@ arc_status arc_get_field(arc_ctx* c, int64_t* dst, int64_t count, void* stream)
     return ARC_OK;
 }
 
+arc_status arc_probe_requests(arc_ctx* c, int64_t items, int64_t cells, uint64_t seed, void* stream,
+                              double* deposits_per_s, double* gathers_per_s)
+{
+    if (!c || !deposits_per_s || !gathers_per_s) return ARC_E_ARG;
+    if (items <= 0) return fail(c, ARC_E_ARG, "items must be > 0");
+    if (!c->have_field || c->last_nb < 2) return fail(c, ARC_E_ARG, "probe needs a previous trace with 2 to 4 bins");
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    const uint64_t nblocked = (uint64_t)c->last_nbx8 * (uint64_t)c->last_nby8 * 512ull *
+                              (uint64_t)((c->last_ncell / ((size_t)c->last_nx * c->last_ny) + 7) / 8);
+    if (cells < 0) return fail(c, ARC_E_ARG, "cells must be >= 0");
+    const uint64_t ncell = cells > 0 ? std::min<uint64_t>((uint64_t)cells, nblocked) : nblocked;
+    float ms = 0.0f;
+    double best_d = 0.0, best_g = 0.0;
+    for (int rep = 0; rep < 3; ++rep) {
+        HIP_TRY(c, hipEventRecord(c->ev[0], st));
+        HIP_TRY(c, launch_probe_deposits(c->J, c->last_nbp, c->last_nb, ncell, (uint64_t)items, seed + rep, c->cus, st));
+        HIP_TRY(c, hipEventRecord(c->ev[1], st));
+        HIP_TRY(c, launch_probe_gathers((const float4*)c->kappa, ncell, (uint64_t)items, seed + rep, (float*)c->acc,
+                                        c->cus, st));
+        HIP_TRY(c, hipEventRecord(c->ev[2], st));
+        HIP_TRY(c, hipEventSynchronize(c->ev[2]));
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+        best_d = std::max(best_d, (double)items / (ms * 1e-3));
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[1], c->ev[2]));
+        best_g = std::max(best_g, (double)items / (ms * 1e-3));
+    }
+    c->have_field = false;  // the field now holds the probe's counts
+    *deposits_per_s = best_d;
+    *gathers_per_s = best_g;
+    return ARC_OK;
+}
+
 arc_status arc_healpix_dirs(arc_ctx* c, int32_t level, float* dst, void* stream)
 {
     if (!c || !dst) return ARC_E_ARG;
@@ -1131,25 +1170,23 @@ arc_status ensure_chem_graphs(arc_ctx* c, const ChemPlan& P)
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-arc_status arc_rt_timestep(arc_ctx* c, const arc_grid* g, const arc_rates* r, const arc_freq_bins* b,
-                           const arc_chem_params* p, double eps, double* dt_n, double* dt_i)
+// Checks and launch arguments of the section 2.9 time step, shared by both entry points;
+// `out` receives the two minima as bit patterns of non-negative doubles.
+arc_status plan_timestep(arc_ctx* c, const arc_grid* g, const arc_rates* r, const arc_freq_bins* b,
+                         const arc_chem_params* p, double eps, unsigned long long* out, TimestepArgs& a)
 {
-    if (!c) return ARC_E_ARG;
-    c->err.clear();
     arc_status rc;
     if ((rc = check_grid(c, g)) != ARC_OK) return rc;
     if ((rc = check_bins(c, b)) != ARC_OK) return rc;
     if (!g->temp) return fail(c, ARC_E_ARG, "null temperature");
     if (!r || !r->gamma) return fail(c, ARC_E_ARG, "null rates");
-    if (!p || !dt_n || !dt_i) return fail(c, ARC_E_ARG, "null params or outputs");
+    if (!p) return fail(c, ARC_E_ARG, "null params");
     if (!(eps > 0) || !std::isfinite(eps)) return fail(c, ARC_E_RANGE, "eps must be finite and > 0");
     if (p->rates != 0 && p->rates != 1) return fail(c, ARC_E_ARG, "rates must be 0 or 1");
     if (p->rates == 0 && !(p->alpha_hii >= 0)) return fail(c, ARC_E_RANGE, "alpha_hii must be >= 0");
-    hipStream_t st = (hipStream_t)p->stream;
-    HIP_TRY(c, hipSetDevice(c->device));
-    TimestepArgs a{};
+    a = TimestepArgs{};
     a.ncell = (uint32_t)((size_t)g->nx * g->ny * g->nz);
     a.y = g->y_he;
     a.cell_cm = g->cell_cm;
@@ -1164,7 +1201,25 @@ arc_status arc_rt_timestep(arc_ctx* c, const arc_grid* g, const arc_rates* r, co
     a.rates = p->rates;
     a.collisional = p->collisional;
     a.alpha_hii = p->alpha_hii;
-    a.out = c->sums;
+    a.out = out;
+    return ARC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+arc_status arc_rt_timestep(arc_ctx* c, const arc_grid* g, const arc_rates* r, const arc_freq_bins* b,
+                           const arc_chem_params* p, double eps, double* dt_n, double* dt_i)
+{
+    if (!c) return ARC_E_ARG;
+    c->err.clear();
+    if (!dt_n || !dt_i) return fail(c, ARC_E_ARG, "null outputs");
+    TimestepArgs a;
+    arc_status rc = plan_timestep(c, g, r, b, p, eps, c->sums, a);
+    if (rc != ARC_OK) return rc;
+    hipStream_t st = (hipStream_t)p->stream;
+    HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, launch_timestep_reset(c->sums, st));
     HIP_TRY(c, launch_timestep(a, c->cus, st));
     unsigned long long h[2];

@@ -37,15 +37,18 @@ __host__ __device__ __forceinline__ uint32_t blocked_index(int x, int y, int z, 
     return (b << 9) | m;
 }
 
-// A crossing's deposit: the cell (blocked index) and the integer amount of every bin.
+// A crossing's deposit: the cell (blocked index) and the amount of every bin in field units,
+// rounded to the field's integers when the wave deposits it.
 template <int NB>
 struct Dep {
     uint32_t cell;        // kNoCell: nothing to deposit
-    long long q[NB];
+    float v[NB];
 };
 
 enum Counter : int {
     kCrossings = 0, kRays, kSplits, kTerminated, kEscapedRays, kSpills, kTreeCount, kQueueOverflow,
+    kDeposits,  // (cell, bins) deposit items issued as atomics after the wave-level merge
+    kCrossingsPre, kDepositsPre,  // crossings and deposits before the persistent launch
     kNumCounters
 };
 
@@ -192,19 +195,6 @@ __device__ __forceinline__ long long round_to_i64(float v)
     const float hi = floorf(r * 2.3283064365386963e-10f);   // r / 2^32, exact scaling
     const float lo = __builtin_fmaf(-hi, 4294967296.0f, r);  // exact remainder in [0, 2^32)
     return (long long)(((unsigned long long)(uint32_t)hi << 32) | (unsigned long long)(uint32_t)lo);
-}
-
-// Mean attenuation over a segment of optical depth x: g(x) = (1 - e^-x) / x, g(0) = 1.
-// Below 0.25 a Taylor series (truncation < 5e-8 relative), above it the hardware
-// exponential (relative error < 1e-6).
-__device__ __forceinline__ float mean_atten(float x)
-{
-    const float series = __builtin_fmaf(
-        x, __builtin_fmaf(x, __builtin_fmaf(x, __builtin_fmaf(x, __builtin_fmaf(x, -1.0f / 720.0f, 1.0f / 120.0f), -1.0f / 24.0f), 1.0f / 6.0f), -0.5f),
-        1.0f);
-    if (x < 0.25f) return series;
-    const float em = __builtin_amdgcn_exp2f(-x * 1.4426950408889634f);
-    return (1.0f - em) * __builtin_amdgcn_rcpf(x);
 }
 
 // e^-tau with the hardware exponential (relative error ~1e-6 for tau up to ~80).
@@ -496,25 +486,29 @@ __device__ __forceinline__ void thin_reach(const TraceArgs& A, const Ray<NB>& ra
 // Photons of one segment (section 2.4, eq:ion per bin): the amount v_b = S ds g(dtau) for the
 // cell in field units, attenuation (compensated tau), then the termination test (a
 // terminating crossing adds the rest of the photons, S / kappa, to v_b) and, with THIN, the
-// thin-radius measurement. Returns kTerminate, kSplit, kEscape or kContinue.
+// thin-radius measurement. T_b carries the transmission e^-tau_b from one segment to the next
+// (one exponential per bin and crossing): with S = w T_b the photons entering the cell, the
+// cell absorbs S (1 - e^-dtau) = w (T_b - T'_b), so v_b = w (T_b - T'_b) / kappa_b, and below
+// dtau = 0.25, where that difference would cancel, S ds g(dtau) with g's Taylor series
+// (truncation < 5e-8 relative). An escaping ray leaves its remaining photons w T'_b in esc.
+// Returns kTerminate, kSplit, kEscape or kContinue.
 template <int NB, int PREC, bool THIN>
 __device__ __forceinline__ int attenuate_seg(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
-                                             LaneStats& st, float v[NB])
+                                             LaneStats& st, float v[NB], float (&T)[NB], float (&esc)[NB])
 {
     bool term = A.tau_term < INFINITY;
     float ts = 0.0f, dts = 0.0f, ks = 1.0f;
+    float rk[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const float dtau = kap[b] * sg.ds;
-        const float taun = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
         if constexpr (THIN) {
             if (b == A.ksoft) {
-                ts = taun;
+                ts = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
                 dts = dtau;
                 ks = kap[b];
             }
         }
-        v[b] = ((ray.w[b] * transmission(taun)) * sg.ds) * mean_atten(dtau);
         if constexpr (PREC == 0) {
             const float s = ray.tau[b] + dtau;
             const float bb = s - ray.tau[b];
@@ -524,6 +518,16 @@ __device__ __forceinline__ int attenuate_seg(const TraceArgs& A, Ray<NB>& ray, c
             ray.tau[b] += dtau;
         }
         const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
+        const float Tn = transmission(taup);
+        // 1 / kappa (hardware reciprocal): used where dtau >= 0.25 or on termination (dtau >= 0.01)
+        rk[b] = __builtin_amdgcn_rcpf(kap[b]);
+        const float g = __builtin_fmaf(
+            dtau, __builtin_fmaf(dtau, __builtin_fmaf(dtau, __builtin_fmaf(dtau, __builtin_fmaf(dtau, -1.0f / 720.0f, 1.0f / 120.0f), -1.0f / 24.0f), 1.0f / 6.0f), -0.5f),
+            1.0f);
+        const float series = ((ray.w[b] * T[b]) * sg.ds) * g;
+        const float lost = (ray.w[b] * (T[b] - Tn)) * rk[b];
+        v[b] = dtau < 0.25f ? series : lost;
+        T[b] = Tn;
         term = term && taup >= A.tau_term && dtau >= kDtauTermMin;
     }
     st.crossings++;
@@ -531,10 +535,7 @@ __device__ __forceinline__ int attenuate_seg(const TraceArgs& A, Ray<NB>& ray, c
     if (term) {
         // absorb what is left in this cell: field += remaining photons / opacity
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-            v[b] += (ray.w[b] * transmission(taup)) / kap[b];
-        }
+        for (int b = 0; b < NB; ++b) v[b] = __builtin_fmaf(ray.w[b] * T[b], rk[b], v[b]);
         st.terminated++;
         return kTerminate;
     }
@@ -546,9 +547,8 @@ __device__ __forceinline__ int attenuate_seg(const TraceArgs& A, Ray<NB>& ray, c
         float tsp = 0.0f;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const float taup = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
-            st.esc[b] += (double)ray.w[b] * (double)transmission(taup);
-            if (b == A.ksoft) tsp = taup;
+            esc[b] = ray.w[b] * T[b];
+            if (b == A.ksoft) tsp = PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b];
         }
         // a ray that leaves the grid while still thin bounds the thin radius by its exit
         if constexpr (THIN)
@@ -559,16 +559,31 @@ __device__ __forceinline__ int attenuate_seg(const TraceArgs& A, Ray<NB>& ray, c
     return kContinue;
 }
 
-// A segment's deposit into its own cell, rounded to the field's integers.
+// Transmission e^-tau of every bin of a ray at its current depth.
+template <int NB, int PREC>
+__device__ __forceinline__ void ray_transmission(const Ray<NB>& ray, float (&T)[NB])
+{
+#pragma unroll
+    for (int b = 0; b < NB; ++b) T[b] = transmission(PREC == 0 ? ray.tau[b] + ray.taulo[b] : ray.tau[b]);
+}
+
+// Photons an escaping lane carried out of the grid, into the FP64 ledger (once per pass).
+template <int NB>
+__device__ __forceinline__ void book_escape(int ev, const float (&esc)[NB], LaneStats& st)
+{
+    if (ev == kEscape) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) st.esc[b] += (double)esc[b];
+    }
+}
+
+// A segment's deposit into its own cell.
 template <int NB, int PREC, bool THIN>
 __device__ __forceinline__ int deposit_seg(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
-                                           LaneStats& st, Dep<NB>& dep)
+                                           LaneStats& st, Dep<NB>& dep, float (&T)[NB], float (&esc)[NB])
 {
-    float v[NB];
-    const int ev = attenuate_seg<NB, PREC, THIN>(A, ray, sg, kap, st, v);
+    const int ev = attenuate_seg<NB, PREC, THIN>(A, ray, sg, kap, st, dep.v, T, esc);
     dep.cell = sg.cell;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) dep.q[b] = round_to_i64(v[b]);
     return ev;
 }
 
@@ -577,6 +592,22 @@ __device__ __forceinline__ int deposit_seg(const TraceArgs& A, Ray<NB>& ray, con
 constexpr float kMovedHiUnit = 1048576.0f;      // 2^20
 constexpr float kMovedLoScale = 4096.0f;        // 2^12
 
+// Integer deposit of an amount v in field units: the field's own integers (kWhole), or the
+// high or low limb of the moved-photon field, hi = floor(v / 2^20) (an integer float) and the
+// rest, v - hi 2^20 (exact: the bits of v below 2^20), in units of 2^-12, rounded.
+enum Limb : int { kWhole = 0, kMovedHi = 1, kMovedLo = 2 };
+template <int LIMB>
+__device__ __forceinline__ long long to_fixed(float v)
+{
+    if constexpr (LIMB == kWhole) {
+        return round_to_i64(v);
+    } else {
+        const float hi = floorf(v * (1.0f / kMovedHiUnit));
+        if constexpr (LIMB == kMovedHi) return round_to_i64(hi);
+        return (long long)(uint32_t)rintf(__builtin_fmaf(-hi, kMovedHiUnit, v) * kMovedLoScale);
+    }
+}
+
 // deposit_seg with the geometric correction (section 2.5): the cell keeps fc of the
 // crossing's photons (the termination remainder included). In mode 2 the rest goes to the
 // neighbour sg.nb, absorbed there at the neighbour's opacity (eq:correction2, the absorber
@@ -584,16 +615,16 @@ constexpr float kMovedLoScale = 4096.0f;        // 2^12
 // photons (1 - fc) v kappa, bounded by the ray's own, are deposited in the two-limb field M
 // and divided by kappa_nb when the rates are formed. A neighbour with no absorber of the bin
 // (kappa_nb = 0) leaves the share in the cell. Modes 1 and 3 drop the removed share.
-// dep: own cell; dh, dl: the neighbour's high and low limbs (kNoCell when all zero).
+// dep: own cell; dm: the photons moved into the neighbour (kNoCell: none).
 template <int NB, int PREC, bool THIN>
 __device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
-                                                const float kapn[NB], LaneStats& st, Dep<NB>& dep, Dep<NB>& dh,
-                                                Dep<NB>& dl)
+                                                const float kapn[NB], LaneStats& st, Dep<NB>& dep, Dep<NB>& dm,
+                                                float (&T)[NB], float (&esc)[NB])
 {
     float v[NB];
-    const int ev = attenuate_seg<NB, PREC, THIN>(A, ray, sg, kap, st, v);
+    const int ev = attenuate_seg<NB, PREC, THIN>(A, ray, sg, kap, st, v, T, esc);
     dep.cell = sg.cell;
-    bool any_hi = false, any_lo = false;
+    dm.cell = sg.nb;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         float keep = v[b], mv = 0.0f;
@@ -605,17 +636,9 @@ __device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray
                 mv = ((1.0f - sg.fc) * v[b]) * kap[b];
             }
         }
-        dep.q[b] = round_to_i64(keep);
-        // mv = hi 2^20 + lo 2^-12: hi = floor(mv / 2^20) (an integer float), and the rest,
-        // mv - hi 2^20 (exact: the bits of mv below 2^20), in units of 2^-12, rounded
-        const float hi = floorf(mv * (1.0f / kMovedHiUnit));
-        dh.q[b] = round_to_i64(hi);
-        dl.q[b] = (long long)(uint32_t)rintf(__builtin_fmaf(-hi, kMovedHiUnit, mv) * kMovedLoScale);
-        any_hi = any_hi || dh.q[b] != 0;
-        any_lo = any_lo || dl.q[b] != 0;
+        dep.v[b] = keep;
+        dm.v[b] = mv;
     }
-    dh.cell = any_hi ? sg.nb : kNoCell;
-    dl.cell = any_lo ? sg.nb : kNoCell;
     return ev;
 }
 
@@ -659,21 +682,25 @@ __device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool
             go = sg[j].event == kContinue;
         }
     }
+    // the gathers are issued unconditionally (cell 0 for a lane without the segment), so that
+    // no branch separates them and each deposit waits for its own gather only
     float kap[K][NB];
 #pragma unroll
-    for (int j = 0; j < K; ++j)
-        if (have[j]) kappa_at<NB>(A, sg[j].cell, kap[j]);
+    for (int j = 0; j < K; ++j) kappa_at<NB>(A, have[j] ? sg[j].cell : 0u, kap[j]);
+    float T[NB], esc[NB];
+    ray_transmission<NB, PREC>(ray, T);
+    // every gather is consumed before the pass issues its first atomic (a wait for a gather
+    // issued before an unknown number of atomics would wait for all of them)
+    static_assert(K % kDepWindow == 0, "whole windows per pass");
+    Dep<NB> dep[K];
 #pragma unroll
-    for (int j0 = 0; j0 < K; j0 += kDepWindow) {
-        Dep<NB> dep[kDepWindow];
-#pragma unroll
-        for (int w = 0; w < kDepWindow; ++w) {
-            const int j = j0 + w;
-            dep[w].cell = kNoCell;
-            if (j < K && have[j] && ev == kContinue) ev = deposit_seg<NB, PREC, THIN>(A, ray, sg[j], kap[j], st, dep[w]);
-        }
-        deposit.add(dep, A.J, A.nbp);
+    for (int j = 0; j < K; ++j) {
+        dep[j].cell = kNoCell;
+        if (have[j] && ev == kContinue) ev = deposit_seg<NB, PREC, THIN>(A, ray, sg[j], kap[j], st, dep[j], T, esc);
     }
+#pragma unroll
+    for (int j0 = 0; j0 < K; j0 += kDepWindow) deposit.template add<kWhole>(dep + j0, A.J, A.nbp);
+    book_escape<NB>(ev, esc, st);
     return ev;
 }
 
@@ -711,29 +738,31 @@ __device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray,
     float kap[K][NB], kapn[K][NB];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
+        const bool hn = have[j] && sg[j].nb != kNoCell;
+        kappa_at<NB>(A, have[j] ? sg[j].cell : 0u, kap[j]);
+        kappa_at<NB>(A, hn ? sg[j].nb : 0u, kapn[j]);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) kapn[j][b] = 0.0f;
-        if (have[j]) {
-            kappa_at<NB>(A, sg[j].cell, kap[j]);
-            if (sg[j].nb != kNoCell) kappa_at<NB>(A, sg[j].nb, kapn[j]);
-        }
+        for (int b = 0; b < NB; ++b) kapn[j][b] = hn ? kapn[j][b] : 0.0f;
+    }
+    float T[NB], esc[NB];
+    ray_transmission<NB, PREC>(ray, T);
+    static_assert(K % 2 == 0, "whole windows per pass");
+    Dep<NB> dep[K], dm[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        dep[j].cell = dm[j].cell = kNoCell;
+        if (have[j] && ev == kContinue)
+            ev = deposit_seg_corr<NB, PREC, THIN>(A, ray, sg[j], kap[j], kapn[j], st, dep[j], dm[j], T, esc);
     }
 #pragma unroll
     for (int j = 0; j < K; j += 2) {
-        Dep<NB> dep[2], dh[2], dl[2];
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            dep[w].cell = dh[w].cell = dl[w].cell = kNoCell;
-            if (j + w < K && have[j + w] && ev == kContinue)
-                ev = deposit_seg_corr<NB, PREC, THIN>(A, ray, sg[j + w], kap[j + w], kapn[j + w], st, dep[w], dh[w],
-                                                     dl[w]);
-        }
-        deposit.add(dep, A.J, A.nbp);
+        deposit.template add<kWhole>(dep + j, A.J, A.nbp);
         if (A.corr == 2) {
-            deposit.add(dh, A.M, 2 * A.nbp);
-            deposit.add(dl, A.M + A.nbp, 2 * A.nbp);
+            deposit.template add<kMovedHi>(dm + j, A.M, 2 * A.nbp);
+            deposit.template add<kMovedLo>(dm + j, A.M + A.nbp, 2 * A.nbp);
         }
     }
+    book_escape<NB>(ev, esc, st);
     return ev;
 }
 
@@ -791,10 +820,13 @@ struct DepScratch {
     unsigned long long q[64 * kDepWindow][NB];
 };
 
-template <int NB>
+template <int NB, int LIMB>
 __device__ __forceinline__ void deposit_wave_plain(const Dep<NB>& d, unsigned long long* base, int stride)
 {
     const int lane = threadIdx.x & 63;
+    long long qd[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) qd[b] = to_fixed<LIMB>(d.v[b]);
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
         const int s = 64 * k + lane;
@@ -803,7 +835,7 @@ __device__ __forceinline__ void deposit_wave_plain(const Dep<NB>& d, unsigned lo
         long long q = 0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const long long qb = __shfl(d.q[b], item, 64);
+            const long long qb = __shfl(qd[b], item, 64);
             q = b == bin ? qb : q;
         }
         if (cell != kNoCell && q != 0) atomicAdd(base + (size_t)cell * (size_t)stride + (size_t)bin, (unsigned long long)q);
@@ -816,19 +848,28 @@ __device__ __forceinline__ void deposit_wave_plain(const Dep<NB>& d, unsigned lo
 // table; items whose cell owns its slot add into the slot's entry, items whose slot was
 // taken by another cell go alone. LDS operations of one wave complete in issue order, and
 // the racy table accesses are volatile so that each read really observes the wave's writes.
-template <int NB>
-__device__ __forceinline__ void deposit_wave_dedup(const Dep<NB> (&d)[kDepWindow], DepScratch<NB>* S,
-                                                   unsigned long long* base, int stride)
+// Items whose integers are all zero are dropped. Returns the number of items issued
+// (wave-uniform).
+template <int NB, int LIMB>
+__device__ __forceinline__ int deposit_wave_dedup(const Dep<NB>* d, DepScratch<NB>* S, unsigned long long* base,
+                                                  int stride)
 {
     constexpr int W = kDepWindow;
     bool v[W];
+    long long q[W][NB];
     bool anyv = false;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        v[w] = d[w].cell != kNoCell;
+        bool nz = false;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            q[w][b] = to_fixed<LIMB>(d[w].v[b]);
+            nz = nz || q[w][b] != 0;
+        }
+        v[w] = d[w].cell != kNoCell && nz;
         anyv = anyv || v[w];
     }
-    if (!__any(anyv)) return;
+    if (!__any(anyv)) return 0;
     // LDS-qualified views: through a generic pointer the accesses would be FLAT instructions,
     // which also wait for the wave's outstanding gathers and atomics
     volatile kLds uint32_t* slot_cell = (volatile kLds uint32_t*)S->slot_cell;
@@ -870,7 +911,7 @@ __device__ __forceinline__ void deposit_wave_dedup(const Dep<NB> (&d)[kDepWindow
         if (rank[w] >= 0) {
             st_cell[rank[w]] = d[w].cell;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) st_q[rank[w] * NB + b] = (unsigned long long)d[w].q[b];
+            for (int b = 0; b < NB; ++b) st_q[rank[w] * NB + b] = (unsigned long long)q[w][b];
         }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
@@ -879,8 +920,8 @@ __device__ __forceinline__ void deposit_wave_dedup(const Dep<NB> (&d)[kDepWindow
             const uint32_t r = slot_rank[h[w]];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
-                if (d[w].q[b] != 0) __hip_atomic_fetch_add(acc_q + r * NB + b, (unsigned long long)d[w].q[b],
-                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                if (q[w][b] != 0) __hip_atomic_fetch_add(acc_q + r * NB + b, (unsigned long long)q[w][b],
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const int tot = n * NB;
@@ -891,6 +932,7 @@ __device__ __forceinline__ void deposit_wave_dedup(const Dep<NB> (&d)[kDepWindow
         if (q != 0) atomicAdd(base + (size_t)cell * (size_t)stride + (size_t)bin, q);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    return n;
 }
 
 // Wave-wide deposit of the crossings of a pass: add() once per window of kDepWindow
@@ -898,14 +940,21 @@ __device__ __forceinline__ void deposit_wave_dedup(const Dep<NB> (&d)[kDepWindow
 template <int NB>
 struct Depositor {
     DepScratch<NB>* scratch;
-    __device__ void add(const Dep<NB> (&d)[kDepWindow], unsigned long long* base, int stride)
+    uint32_t items = 0;  // deposit items issued by this wave (wave-uniform)
+    // the kDepWindow items d[0 .. kDepWindow) of every lane, as integers of limb LIMB
+    template <int LIMB>
+    __device__ void add(const Dep<NB>* d, unsigned long long* base, int stride)
     {
         if constexpr (ARC_DEDUP == 1) {
-            deposit_wave_dedup<NB>(d, scratch, base, stride);
+            items += (uint32_t)deposit_wave_dedup<NB, LIMB>(d, scratch, base, stride);
         } else {
 #pragma unroll
-            for (int w = 0; w < kDepWindow; ++w) deposit_wave_plain<NB>(d[w], base, stride);
+            for (int w = 0; w < kDepWindow; ++w) deposit_wave_plain<NB, LIMB>(d[w], base, stride);
         }
+    }
+    __device__ void flush(const TraceArgs& A) const
+    {
+        if ((threadIdx.x & 63) == 0 && items) atomicAdd(&A.counters[kDeposits], (unsigned long long)items);
     }
 };
 

@@ -69,6 +69,7 @@ struct ChemArgs {
 hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
+hipError_t launch_snapshot_counters(unsigned long long* counters, hipStream_t s);
 // out[0] = sum J[i], out[1] = sum J[i] (2i + 1), both mod 2^64; out must be zeroed first.
 hipError_t launch_field_checksum(const unsigned long long* J, size_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_opacity(const OpacityArgs& a, hipStream_t s);
@@ -89,6 +90,10 @@ hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* i
                                    int refill, hipStream_t s);
 int persistent_max_waves();
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_probe_deposits(unsigned long long* J, int nbp, int nb, uint64_t ncell, uint64_t items,
+                                 uint64_t seed, int cus, hipStream_t s);
+hipError_t launch_probe_gathers(const float4* kappa, uint64_t ncell, uint64_t items, uint64_t seed, float* sink,
+                                int cus, hipStream_t s);
 hipError_t launch_get_field(const unsigned long long* J, const unsigned long long* M, int nb, int nbp, int nx, int ny,
                             int nbx8, int nby8, uint32_t ncell, long long* dst, hipStream_t s);
 // cus: compute units of the device (the solver launches resident waves only)

@@ -76,6 +76,19 @@ hipError_t launch_field_checksum(const unsigned long long* J, size_t n, unsigned
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
+// Counters of the work done before the persistent launch (its own work is the difference).
+__global__ void k_snapshot_counters(unsigned long long* c)
+{
+    c[kCrossingsPre] = c[kCrossings];
+    c[kDepositsPre] = c[kDeposits];
+}
+
+hipError_t launch_snapshot_counters(unsigned long long* counters, hipStream_t s)
+{
+    k_snapshot_counters<<<1, 1, 0, s>>>(counters);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s)
 {
     k_set_u32<<<1, 1, 0, s>>>(p, v);
@@ -463,6 +476,7 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
         }
     }
     flush_stats<NB>(A, st);
+    dep.flush(A);
 }
 
 template <int NB>
@@ -633,6 +647,7 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
         if (ev == kTerminate || ev == kEscape) has = false;
     }
     flush_stats<NB>(A, st);
+    dep.flush(A);
     if (lane == 0 && spilled) atomicAdd(&A.counters[kSpills], (unsigned long long)spilled);
 }
 
@@ -676,6 +691,59 @@ hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* i
         case 3: return persistent_variant<3>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
         default: return persistent_variant<4>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
     }
+}
+
+// -------------------------------------------------------------------------------------
+// Request-rate probes (measurement only): random single-sector int64 atomic deposits and
+// random 16-byte gathers over the trace's own buffers, to hold the trace kernel against.
+// Cells come from a counter-based hash (splitmix64 finaliser) of the item index.
+// -------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Item i adds 1 to the NB bins of cell hash(i) mod ncell, its bins in NB adjacent lanes of
+// one instruction (as the trace's deposits are issued).
+__global__ __launch_bounds__(256) void k_probe_deposits(unsigned long long* J, int nbp, int nb, uint64_t ncell,
+                                                         uint64_t items, uint64_t seed)
+{
+    const uint64_t lanes = items * (uint64_t)nb;
+    for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < lanes; s += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t item = s / (uint64_t)nb;
+        const int bin = (int)(s - item * (uint64_t)nb);
+        const uint64_t cell = mix64(seed + item) % ncell;
+        atomicAdd(J + cell * (uint64_t)nbp + bin, 1ull);
+    }
+}
+
+// Item i reads the 16-byte opacity record of cell hash(i) mod ncell; the sum of what a lane
+// read is stored only if it is negative (never, opacities are >= 0), so the reads stay.
+__global__ __launch_bounds__(256) void k_probe_gathers(const float4* kappa, uint64_t ncell, uint64_t items,
+                                                        uint64_t seed, float* sink)
+{
+    float acc = 0.0f;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < items; i += (uint64_t)gridDim.x * blockDim.x) {
+        const float4 v = kappa[mix64(seed + i) % ncell];
+        acc += v.x + v.y + v.z;
+    }
+    if (acc < 0.0f) sink[0] = acc;
+}
+
+hipError_t launch_probe_deposits(unsigned long long* J, int nbp, int nb, uint64_t ncell, uint64_t items,
+                                 uint64_t seed, int cus, hipStream_t s)
+{
+    k_probe_deposits<<<cus * 32, 256, 0, s>>>(J, nbp, nb, ncell, items, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_gathers(const float4* kappa, uint64_t ncell, uint64_t items, uint64_t seed, float* sink,
+                                int cus, hipStream_t s)
+{
+    k_probe_gathers<<<cus * 32, 256, 0, s>>>(kappa, ncell, items, seed, sink);
+    return hipGetLastError();
 }
 
 // -------------------------------------------------------------------------------------
