@@ -378,14 +378,18 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     // (the photon rate through any sphere is at most S_b and a cell is at most sqrt(3)
     // long), plus a remainder below eps_term S_b sqrt(3) / 0.01 on termination, plus with
     // the optically thin fill at most S_b / pi (r >= 1/2). The sum over sources therefore
-    // stays below 2^62 units. The moved photons of the conserving correction are counted in
-    // the same unit: all of them together are at most the photons emitted.
+    // stays below 2^62 units. With the conserving correction a cell also receives into its
+    // field at most half of each of its six neighbours' deposits times the opacity ratio
+    // kMovedRatioJ: 1 + 6 * 16 / 2 = 49 times the bound (larger ratios move photons into the
+    // moved-photon field, counted in the same unit: all of them together are at most the
+    // photons emitted).
     for (int k = 0; k < kMaxBins; ++k) P.uj[k] = 1.0;
     for (int i = 0; i < s->n; ++i) P.sum_ndot += s->ndot[i];
+    const double corr_factor = p->correction == ARC_CORR_CONSERVING ? 1.0 + 6.0 * (double)kMovedRatioJ / 2.0 : 1.0;
     for (int k = 0; k < nb; ++k) {
         const double bound = (std::sqrt(3.0) + p->eps_term * std::sqrt(3.0) / (double)kDtauTermMin +
                               (thin ? 1.0 / M_PI : 0.0)) *
-                             P.sum_ndot * b->frac[k] * (1.0 + 1e-6);
+                             P.sum_ndot * b->frac[k] * (1.0 + 1e-6) * corr_factor;
         const double need = bound / 4611686018427387904.0;  // 2^62
         if (p->u_j_override > 0) {
             if (p->u_j_override < need)
@@ -1062,7 +1066,7 @@ arc_status arc_probe_requests(arc_ctx* c, int64_t items, int64_t cells, uint64_t
 {
     if (!c || !deposits_per_s || !gathers_per_s) return ARC_E_ARG;
     if (items <= 0) return fail(c, ARC_E_ARG, "items must be > 0");
-    if (!c->have_field || c->last_nb < 2) return fail(c, ARC_E_ARG, "probe needs a previous trace with 2 to 4 bins");
+    if (c->last_nb < 2 || !c->J || !c->kappa) return fail(c, ARC_E_ARG, "probe needs a previous trace with 2 to 4 bins");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(c, hipSetDevice(c->device));
     const uint64_t nblocked = (uint64_t)c->last_nbx8 * (uint64_t)c->last_nby8 * 512ull *

@@ -608,37 +608,52 @@ __device__ __forceinline__ long long to_fixed(float v)
     }
 }
 
+// Opacity ratio up to which the conserving correction's moved share enters the neighbour's
+// field directly (beyond it, as photons in the two-limb field M).
+constexpr float kMovedRatioJ = 16.0f;
+
 // deposit_seg with the geometric correction (section 2.5): the cell keeps fc of the
 // crossing's photons (the termination remainder included). In mode 2 the rest goes to the
 // neighbour sg.nb, absorbed there at the neighbour's opacity (eq:correction2, the absorber
-// ratio per bin as the opacity ratio kappa / kappa_nb), whatever that ratio: the moved
-// photons (1 - fc) v kappa, bounded by the ray's own, are deposited in the two-limb field M
-// and divided by kappa_nb when the rates are formed. A neighbour with no absorber of the bin
-// (kappa_nb = 0) leaves the share in the cell. Modes 1 and 3 drop the removed share.
-// dep: own cell; dm: the photons moved into the neighbour (kNoCell: none).
+// ratio per bin as the opacity ratio kappa / kappa_nb), whatever that ratio. Up to a ratio of
+// kMovedRatioJ it enters the neighbour's field directly, (1 - fc) v kappa / kappa_nb (dj);
+// beyond it the moved photons, (1 - fc) v kappa (bounded by the ray's own), go to the
+// two-limb field M (dm) and are divided by kappa_nb when the rates are formed. A neighbour
+// with no absorber of the bin (kappa_nb = 0) leaves the share in the cell. Modes 1 and 3
+// drop the removed share. dj and dm name the neighbour only when some bin uses them.
 template <int NB, int PREC, bool THIN>
 __device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray, const Seg& sg, const float kap[NB],
-                                                const float kapn[NB], LaneStats& st, Dep<NB>& dep, Dep<NB>& dm,
-                                                float (&T)[NB], float (&esc)[NB])
+                                                const float kapn[NB], LaneStats& st, Dep<NB>& dep, Dep<NB>& dj,
+                                                Dep<NB>& dm, float (&T)[NB], float (&esc)[NB])
 {
     float v[NB];
     const int ev = attenuate_seg<NB, PREC, THIN>(A, ray, sg, kap, st, v, T, esc);
-    dep.cell = sg.cell;
-    dm.cell = sg.nb;
+    bool use_j = false, use_m = false;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        float keep = v[b], mv = 0.0f;
+        float keep = v[b], mj = 0.0f, mm = 0.0f;
         if (sg.fc < 1.0f) {
             if (sg.nb == kNoCell) {
                 keep = sg.fc * v[b];
             } else if (kapn[b] > 0.0f) {
                 keep = sg.fc * v[b];
-                mv = ((1.0f - sg.fc) * v[b]) * kap[b];
+                const float moved = (1.0f - sg.fc) * v[b];
+                if (kap[b] <= kMovedRatioJ * kapn[b]) {
+                    mj = moved * (kap[b] / kapn[b]);
+                    use_j = true;
+                } else {
+                    mm = moved * kap[b];
+                    use_m = true;
+                }
             }
         }
         dep.v[b] = keep;
-        dm.v[b] = mv;
+        dj.v[b] = mj;
+        dm.v[b] = mm;
     }
+    dep.cell = sg.cell;
+    dj.cell = use_j ? sg.nb : kNoCell;
+    dm.cell = use_m ? sg.nb : kNoCell;
     return ev;
 }
 
@@ -747,17 +762,18 @@ __device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray,
     float T[NB], esc[NB];
     ray_transmission<NB, PREC>(ray, T);
     static_assert(K % 2 == 0, "whole windows per pass");
-    Dep<NB> dep[K], dm[K];
+    Dep<NB> dep[K], dj[K], dm[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        dep[j].cell = dm[j].cell = kNoCell;
+        dep[j].cell = dj[j].cell = dm[j].cell = kNoCell;
         if (have[j] && ev == kContinue)
-            ev = deposit_seg_corr<NB, PREC, THIN>(A, ray, sg[j], kap[j], kapn[j], st, dep[j], dm[j], T, esc);
+            ev = deposit_seg_corr<NB, PREC, THIN>(A, ray, sg[j], kap[j], kapn[j], st, dep[j], dj[j], dm[j], T, esc);
     }
 #pragma unroll
     for (int j = 0; j < K; j += 2) {
         deposit.template add<kWhole>(dep + j, A.J, A.nbp);
         if (A.corr == 2) {
+            deposit.template add<kWhole>(dj + j, A.J, A.nbp);
             deposit.template add<kMovedHi>(dm + j, A.M, 2 * A.nbp);
             deposit.template add<kMovedLo>(dm + j, A.M + A.nbp, 2 * A.nbp);
         }
@@ -856,8 +872,12 @@ __device__ __forceinline__ int deposit_wave_dedup(const Dep<NB>* d, DepScratch<N
 {
     constexpr int W = kDepWindow;
     bool v[W];
-    long long q[W][NB];
     bool anyv = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) anyv = anyv || d[w].cell != kNoCell;
+    if (!__any(anyv)) return 0;
+    long long q[W][NB];
+    anyv = false;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         bool nz = false;
