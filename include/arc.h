@@ -347,6 +347,19 @@ arc_status arc_rt_timestep(arc_ctx* ctx, const arc_grid* grid, const arc_rates* 
                            const arc_freq_bins* bins, const arc_chem_params* params, double eps,
                            double* dt_n, double* dt_i);
 
+/* arc_rt_timestep for callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops): the same minima, computed by the same kernels,
+ * but held in a small static device array of the library (256 bytes per GPU, kept until
+ * the process ends) instead of the context's memory, and written as doubles to the caller's
+ * device array dt_out[2] = (dt_n, dt_i) in seconds, stream-ordered on params->stream; the
+ * call neither allocates nor blocks. The array's size does not depend on the grid (two
+ * words are used; grids are bounded as for every call, below 2^31 cells). All calls on one
+ * GPU share its array: calls that overlap on one GPU (different streams without ordering)
+ * race and must not be made. */
+arc_status arc_rt_timestep_noalloc(arc_ctx* ctx, const arc_grid* grid, const arc_rates* rates,
+                                   const arc_freq_bins* bins, const arc_chem_params* params, double eps,
+                                   double* dt_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -131,6 +131,9 @@ def lib():
         L.arc_rt_timestep.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Rates), C.POINTER(Bins),
                                       C.POINTER(ChemParams), C.c_double, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
+        L.arc_rt_timestep_noalloc.restype = C.c_int32
+        L.arc_rt_timestep_noalloc.argtypes = [C.c_void_p, C.POINTER(Grid), C.POINTER(Rates), C.POINTER(Bins),
+                                              C.POINTER(ChemParams), C.c_double, C.c_void_p]
         L.arc_mlp_create.restype = C.c_int32
         L.arc_mlp_create.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
         L.arc_mlp_destroy.restype = None
@@ -315,6 +318,22 @@ class Context:
         self._check(lib().arc_rt_timestep(self._h, C.byref(g), C.byref(r), C.byref(b), C.byref(p), float(eps),
                                           C.byref(dn), C.byref(di)))
         return dn.value, di.value
+
+
+    def rt_timestep_noalloc(self, grid, gamma, bins: dict, dt_out, eps=0.1, rates=1, collisional=1,
+                            alpha_hii=2.59e-13, stream=None):
+        """arc_rt_timestep_noalloc: (dt_n, dt_I) in seconds into the device float64 tensor
+        dt_out[2], stream-ordered, without allocating or blocking."""
+        if dt_out.dtype.itemsize != 8 or dt_out.numel() < 2:
+            raise ValueError("dt_out must be a device float64 tensor of at least 2 entries")
+        g = _grid(grid)
+        r = Rates(_ptr(gamma), 0)
+        b, _keep = _bins_struct(bins)
+        p = ChemParams(0, int(rates), int(collisional), float(alpha_hii), 0.1, 1, 1.0, 0, _stream(stream), None,
+                       0.0, 0, 0)
+        self._check(lib().arc_rt_timestep_noalloc(self._h, C.byref(g), C.byref(r), C.byref(b), C.byref(p),
+                                                  float(eps), _ptr(dt_out)))
+        return dt_out
 
 
 def _bins_struct(bins):

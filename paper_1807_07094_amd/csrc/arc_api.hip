@@ -73,12 +73,21 @@ struct arc_ctx {
     hipGraphExec_t cexec[3] = {nullptr, nullptr, nullptr};
     std::vector<unsigned char> chem_key;
     unsigned long long* sums = nullptr;  // field checksums of the autotuner
+    unsigned long long* static_scratch = nullptr;  // this device's copy of `scratch`
     struct Tuned {
         int nx, ny, nz, nb, level0, lmax, precision;
         arc_tune_result shape;
     };
     std::vector<Tuned> tuned;
 };
+
+// Scratch of the allocation-free entry point (arc_rt_timestep_noalloc): a file-scope device
+// array, one copy per GPU, held until the process ends. Host code never passes its name to
+// a kernel (on the host the name is a stand-in, not a device address): each context
+// resolves the device's copy once, at creation, with hipGetSymbolAddress, and uses that.
+constexpr int kStaticScratchWords = 32;  // 256 bytes
+constexpr int kTimestepScratchWords = 2; // the two grid minima of section 2.9
+static __device__ __align__(256) unsigned long long scratch[kStaticScratchWords];
 
 namespace {
 
@@ -242,6 +251,11 @@ arc_status arc_create(int32_t device, arc_ctx** out)
     }
     c->cus = prop.multiProcessorCount;
     c->item_bytes = prop.totalGlobalMem / 6;
+    // this device's copy of the static scratch (the device is current)
+    if (hipGetSymbolAddress((void**)&c->static_scratch, HIP_SYMBOL(scratch)) != hipSuccess || !c->static_scratch) {
+        delete c;
+        return ARC_E_DEVICE;
+    }
     bool ok = hipMalloc((void**)&c->counters, kNumCounters * sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc((void**)&c->acc, 8 * sizeof(double)) == hipSuccess &&
               hipMalloc((void**)&c->u32, 4 * sizeof(uint32_t)) == hipSuccess &&
@@ -1231,6 +1245,28 @@ arc_status arc_rt_timestep(arc_ctx* c, const arc_grid* g, const arc_rates* r, co
     HIP_TRY(c, hipStreamSynchronize(st));
     std::memcpy(dt_n, &h[0], sizeof(double));
     std::memcpy(dt_i, &h[1], sizeof(double));
+    return ARC_OK;
+}
+
+arc_status arc_rt_timestep_noalloc(arc_ctx* c, const arc_grid* g, const arc_rates* r, const arc_freq_bins* b,
+                                   const arc_chem_params* p, double eps, double* dt_out)
+{
+    if (!c) return ARC_E_ARG;
+    c->err.clear();
+    if (!dt_out) return fail(c, ARC_E_ARG, "null output");
+    if (!c->static_scratch) return fail(c, ARC_E_DEVICE, "static scratch of device %d not resolved", c->device);
+    // the kernels use kTimestepScratchWords words of the device's static scratch, whatever the
+    // grid; grids are bounded by the checks every entry point applies (below 2^31 cells)
+    static_assert(kTimestepScratchWords <= kStaticScratchWords, "static scratch too small");
+    TimestepArgs a;
+    arc_status rc = plan_timestep(c, g, r, b, p, eps, c->static_scratch, a);
+    if (rc != ARC_OK) return rc;
+    hipStream_t st = (hipStream_t)p->stream;
+    HIP_TRY(c, hipSetDevice(c->device));
+    // the array keeps the last call's minima: reset them (a kernel, not a memset node)
+    HIP_TRY(c, launch_timestep_reset(c->static_scratch, st));
+    HIP_TRY(c, launch_timestep(a, c->cus, st));
+    HIP_TRY(c, launch_timestep_publish(c->static_scratch, dt_out, st));
     return ARC_OK;
 }
 

@@ -281,6 +281,18 @@ __global__ __launch_bounds__(256) void k_timestep(TimestepArgs a)
     }
 }
 
+// The two minima as doubles into caller memory (device pointer out[2]).
+__global__ void k_timestep_publish(const unsigned long long* bits, double* out)
+{
+    if (threadIdx.x < 2) out[threadIdx.x] = __longlong_as_double((long long)bits[threadIdx.x]);
+}
+
+hipError_t launch_timestep_publish(const unsigned long long* bits, double* out, hipStream_t s)
+{
+    k_timestep_publish<<<1, 64, 0, s>>>(bits, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_timestep(const TimestepArgs& a, int cus, hipStream_t s)
 {
     const size_t want = ((size_t)a.ncell + 255) / 256;

@@ -112,5 +112,6 @@ struct TimestepArgs {
 };
 hipError_t launch_timestep_reset(unsigned long long* out, hipStream_t s);
 hipError_t launch_timestep(const TimestepArgs& a, int cus, hipStream_t s);
+hipError_t launch_timestep_publish(const unsigned long long* bits, double* out, hipStream_t s);
 
 }  // namespace arc
