@@ -22,17 +22,24 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# HBM bytes per crossing of the trace kernel from rocprofv3 FETCH_SIZE (x2.0, calibrated on a copy)
-# and WRITE_SIZE (x1.0) on this workload, valid for the kernel sources with these digests; with
-# any other sources the figure is stale and the traffic is reported as null.
-MEASURED_TRAFFIC = {
-    "bytes_per_crossing": 21.90,
+# Counters of the trace kernel on this workload (rocprofv3, one launch from the generated state):
+# HBM bytes per crossing from FETCH_SIZE (x2.0, calibrated on a copy) and WRITE_SIZE (x1.0), VALU
+# wave-instructions per crossing (SQ_INSTS_VALU) and the L2 hit rate (TCC_HIT_sum, TCC_MISS_sum).
+# Valid for the kernel sources with these digests; with any other sources they are stale and
+# reported as null.
+MEASURED_COUNTERS = {
+    "bytes_per_crossing": None,
+    "valu_per_crossing": None,
+    "l2_hit_rate": None,
     "sha256": {
-        "paper_1807_07094_amd/csrc/arc_device.h": "a3eba0065b7c861299c1f3032ce8ae155c8ca81f13239c1f348cb854e38a6fc5",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "46699469772a00ba8d4ee8ea8a2b5dadec2904f7f5afdb5d9567e7848ad42e9f",
+        "paper_1807_07094_amd/csrc/arc_device.h": "",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "",
     },
-    "profile": "profiles/hbm_traffic_grf1024_16384src.md",
+    "profile": "profiles/hbm_l2_sq_k_trace_persistent_grf1024_16384src.md",
 }
+# VALU issue of the whole chip: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every four
+# cycles (16 lanes wide), at 2.4 GHz: 6.14e11 wave-instructions per second.
+VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
 
 def host_cpu_model():
@@ -46,14 +53,15 @@ def host_cpu_model():
     return None
 
 
-def measured_traffic_per_crossing():
+def measured_counters():
+    """The profiled counter figures if the kernel sources are the profiled ones, else None."""
     import hashlib
 
-    for rel, digest in MEASURED_TRAFFIC["sha256"].items():
+    for rel, digest in MEASURED_COUNTERS["sha256"].items():
         with open(os.path.join(ROOT, rel), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
-    return MEASURED_TRAFFIC["bytes_per_crossing"]
+    return MEASURED_COUNTERS
 
 
 def log(msg):
@@ -269,13 +277,25 @@ def main():
     per_launch = float(np.mean([l["kernel_crossings"] if batched else l["crossings"] for l in leds]))
     deposits_per_launch = float(np.mean([l["kernel_deposits"] if batched else l["deposits"] for l in leds]))
     achieved = per_launch * bpc / (kms * 1e-3) / 1e9
-    tpc = measured_traffic_per_crossing() if args.config == 4 and args.schedule == "batched" else None
+    mc = measured_counters() if args.config == 4 and args.schedule == "batched" and args.precision == "fp32_comp" \
+        else None
+    tpc = mc["bytes_per_crossing"] if mc else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(tpc * per_launch) if tpc is not None else None,
                 "traffic_unit": "bytes per launch", "traffic_bytes_per_crossing": tpc,
                 "kernel": "k_trace_persistent" if args.schedule == "batched" else "k_trace_rays",
                 "kernel_ms": round(kms, 3), "bytes_per_crossing": bpc}
+    if mc:
+        # what the counters say limits the kernel: the HBM traffic it really moves, and its VALU
+        # issue against the chip's (profiled instructions per crossing at this launch's rate)
+        valu_rate = mc["valu_per_crossing"] * per_launch / (kms * 1e-3)
+        roofline["counters"] = {
+            "hbm_traffic_gbs": round(tpc * per_launch / (kms * 1e-3) / 1e9, 1),
+            "hbm_traffic_frac": round(tpc * per_launch / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "valu_wave_instr_per_crossing": mc["valu_per_crossing"],
+            "valu_issue_frac": round(valu_rate / VALU_PEAK_WAVE_INSTR_PER_S, 4),
+            "l2_hit_rate": mc["l2_hit_rate"], "profile": mc["profile"]}
 
     crossings_step = float(np.mean([l["crossings"] for l in leds]))
     extra = {"trace_crossings_per_s": round(crossings_step / (float(np.mean([l["ms_total"] for l in leds])) * 1e-3), 1),
