@@ -11,7 +11,11 @@ Gnedin 1997 fits it cites are not available here, so each pin comes from elsewhe
 * the Rybicki & Lightman (1979) free-free emissivity 1.4e-27 T^1/2 Z^2 g_B with a
   frequency-averaged Gaunt factor between 1.1 and 1.5;
 * energy conservation of the photoheating: the heat deposited plus the ionisation energy
-  equals the energy of the photons absorbed along the rays.
+  equals the energy of the photons absorbed along the rays;
+* He+ recombination: Osterbrock & Ferland's tabulated case-B value at 1e4 K, and the
+  dielectronic term against Aldrovandi & Pequignot's (1973) published constants;
+* the collisional-equilibrium cooling curve of H + He gas: its hydrogen and He+ peaks where
+  the literature puts them (this exercises the excitation cooling, which no other pin does).
 """
 import math
 
@@ -117,3 +121,50 @@ def test_heating_conserves_photon_energy_below_helium_thresholds():
             "e_thr": np.array(W.E_THR_EV) * W.EV_ERG}
     deposited, absorbed = heating_identity(bins, 0.7, 0.5, 0.4)
     assert deposited == pytest.approx(e * W.EV_ERG * absorbed, rel=1e-10)
+
+
+def test_helium_recombination_against_tabulated_value():
+    """Radiative recombination of He+ at 1e4 K (the dielectronic term is negligible there):
+    Osterbrock & Ferland (2006) tabulate alpha_B(He0) = 2.73e-13 cm^3/s."""
+    assert oracle.rate_coeffs(1e4)[1] == pytest.approx(2.73e-13, rel=0.1)
+
+
+@pytest.mark.parametrize("T", [5e4, 1e5, 2e5, 5e5, 1e6])
+def test_helium_dielectronic_recombination_against_its_published_constants(T):
+    """The dielectronic part of alpha_HeII (what remains after the radiative fit, which is
+    below 2% of it from 1e5 K) against Aldrovandi & Pequignot (1973):
+    1.9e-3 T^-3/2 exp(-4.7e5/T) (1 + 0.3 exp(-9.4e4/T))."""
+    rad = 1.26e-14 * (2 * 285335.4 / T) ** 0.75
+    diel = oracle.rate_coeffs(T)[1] - rad
+    ap = 1.9e-3 * T ** -1.5 * math.exp(-4.7e5 / T) * (1 + 0.3 * math.exp(-9.4e4 / T))
+    assert diel == pytest.approx(ap, rel=0.1)
+
+
+def cie_cooling_curve(y=0.08):
+    """Cooling per n_H^2 of H + He gas in collisional ionisation equilibrium (ionisation =
+    recombination for every ion), from the oracle's rates and cooling."""
+    Ts = np.logspace(3.9, 6.0, 400)
+    lam = []
+    for T in Ts:
+        k = oracle.rate_coeffs(T)
+        xhii = k[3] / (k[3] + k[0])
+        r1, r2 = k[4] / k[1], k[5] / k[2]
+        f = np.array([1.0, r1, r1 * r2])
+        f /= f.sum()
+        nhei, nheii, nheiii = y * f
+        ne = xhii + nheii + 2 * nheiii
+        lam.append(oracle.cooling(T, ne, 1 - xhii, xhii, nhei, nheii, nheiii))
+    return Ts, np.array(lam)
+
+
+def test_collisional_equilibrium_cooling_curve_has_the_hydrogen_and_helium_peaks():
+    """The textbook shape of primordial-gas cooling in collisional equilibrium (e.g. Katz,
+    Weinberg & Hernquist 1996): a hydrogen peak (Lyman-alpha excitation) near 2e4 K of about
+    1e-22 erg cm^3/s per n_H^2 and a He+ peak near 1e5 K a few times lower. A dropped
+    excitation term, a wrong exponent or threshold moves or removes a peak."""
+    Ts, lam = cie_cooling_curve()
+    peaks = [i for i in range(1, len(lam) - 1) if lam[i] > lam[i - 1] and lam[i] > lam[i + 1]]
+    assert len(peaks) == 2, [Ts[i] for i in peaks]
+    th, tp = Ts[peaks[0]], Ts[peaks[1]]
+    assert 1.3e4 < th < 2.5e4 and 4e-23 < lam[peaks[0]] < 1.5e-22
+    assert 6e4 < tp < 1.5e5 and 1e-23 < lam[peaks[1]] < lam[peaks[0]]
