@@ -342,7 +342,8 @@ __device__ __forceinline__ void geom_correction(const TraceArgs& A, const Ray<NB
         }
     }
     if (!(dmin < 0.5 * lpix)) return;
-    double fc = 0.5 + dmin / lpix;
+    // the decisions above are FP64; the share itself needs FP32 only
+    float fc = 0.5f + (float)dmin * __builtin_amdgcn_rcpf((float)lpix);
     if (A.corr == 3) fc *= fc;
     if (A.corr == 2) {
         // the neighbour's per-axis term replaces the cell's along `axis` (static indices only:
@@ -361,7 +362,7 @@ __device__ __forceinline__ void geom_correction(const TraceArgs& A, const Ray<NB
         if (!inside) return;  // no neighbour inside: the cell keeps everything
         sg.nb = nb;
     }
-    sg.fc = (float)fc;
+    sg.fc = fc;
 }
 
 // Geometry of the next segment (section 2.4: the step to the next x, y or z boundary, or
@@ -660,7 +661,7 @@ __device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray
 // Segments whose geometry is computed ahead of their deposits (opacity loads in flight
 // per lane).
 #ifndef ARC_SEG_AHEAD
-#define ARC_SEG_AHEAD 8
+#define ARC_SEG_AHEAD 10
 #endif
 constexpr int kSegAhead = ARC_SEG_AHEAD;
 #ifndef ARC_DEP_WINDOW

@@ -655,6 +655,11 @@ constexpr int kMaxWavesPerBlock = 8;
 
 int persistent_max_waves() { return kMaxWavesPerBlock; }
 
+// LDS of a persistent workgroup of WPB waves (ray stacks and deposit scratch).
+template <int NB, int WPB>
+constexpr size_t persistent_lds_bytes() { return (size_t)WPB * (kStackCap * sizeof(StackRec<NB>) + sizeof(DepScratch<NB>)); }
+constexpr size_t kLdsPerCu = 163840;
+
 template <int NB, int PREC, bool CORR, bool THIN>
 static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const uint32_t* n_items, uint32_t* head,
                                 RayRec* spill, uint32_t spill_cap, int blocks, int waves, int refill, hipStream_t s)
@@ -663,7 +668,13 @@ static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const u
         case 1: k_trace_persistent<NB, PREC, 1, CORR, THIN><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
         case 2: k_trace_persistent<NB, PREC, 2, CORR, THIN><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
         case 4: k_trace_persistent<NB, PREC, 4, CORR, THIN><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        default: k_trace_persistent<NB, PREC, 8, CORR, THIN><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        default:
+            // eight waves only where their LDS fits a compute unit (else four, in twice the blocks)
+            if constexpr (persistent_lds_bytes<NB, 8>() <= kLdsPerCu)
+                k_trace_persistent<NB, PREC, 8, CORR, THIN><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill);
+            else
+                k_trace_persistent<NB, PREC, 4, CORR, THIN><<<2 * blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill);
+            break;
     }
     return hipGetLastError();
 }

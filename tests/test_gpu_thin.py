@@ -120,3 +120,23 @@ def test_thin_argument_checks(arc, ctx):
         with pytest.raises(arc.ArcError) as e:
             run_gpu_trace(arc, ctx, w)
         assert e.value.status == -2
+
+
+def test_thin_graph_replays_equal_eager(arc, ctx):
+    """Recorded graphs with thin spheres: the radii are read from device memory at every
+    replay, so a replay with new radii (the same fill shape) equals an eager trace with them,
+    and the measured radii too."""
+    w = thin_workload(seed=49, radii=(0.0, 2.0, 5.5, 8.0, 3.0))
+    out = []
+    for radii in ((0.0, 2.0, 5.5, 8.0, 3.0), (1.0, 2.5, 5.0, 7.5, 3.5), (0.0, 2.0, 5.5, 8.0, 3.0)):
+        w.sources["r_thin"] = np.array(radii)
+        res = {}
+        for graph in (True, False):
+            w.sources["r_thin_out"] = np.empty(5)
+            g = run_gpu_trace(arc, ctx, w, graph=graph)
+            res[graph] = (g["J"], w.sources["r_thin_out"].copy(), g["ledger"]["absorbed_thin"])
+        assert np.array_equal(res[True][0], res[False][0])
+        assert np.array_equal(res[True][1], res[False][1])
+        assert res[True][2] == pytest.approx(res[False][2], rel=1e-12)
+        out.append(res[True][0])
+    assert np.array_equal(out[0], out[2]) and not np.array_equal(out[0], out[1])
