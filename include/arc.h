@@ -124,7 +124,7 @@ typedef struct {
     void* stream;          /* hipStream_t, NULL = default stream */
     int32_t tune_waves;    /* batched: waves per workgroup (0 = default) */
     int32_t tune_blocks;   /* batched: workgroups in the persistent grid (0 = default) */
-    int32_t tune_refill;   /* batched: refill a wave once this many lanes idle (0 = 32) */
+    int32_t tune_refill;   /* batched: refill a wave once this many lanes idle (0 = 48) */
     int32_t tune_item_level; /* batched: HEALPix level whose rays become the persistent
                                 launch's work items; earlier levels are traced level by
                                 level (0 = five levels below the first). Lowered while the

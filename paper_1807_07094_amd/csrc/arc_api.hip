@@ -561,6 +561,13 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
 // from 1.4e8 to 4e5). Lowered while the larger ray buffer would exceed item_bytes.
 constexpr int kDefaultItemDepth = 5;
 
+// Default refill threshold of the persistent launch: a wave refills only once all its lanes
+// are idle, so that its rays, mostly children of the same splits, start together and their
+// merged deposits make fewer atomics (1024^3 x 16384 sources from the generated state: refill
+// at 32, 48 and 64 idle lanes, 0.283, 0.273 and 0.261 deposit items per crossing, 744, 718 and
+// 712 ms).
+constexpr int kDefaultRefill = 64;
+
 // Records of a ray buffer, without keeping its contents.
 hipError_t grow_rays(arc_ctx* c, int i, size_t n)
 {
@@ -908,7 +915,7 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
     if (p->schedule == ARC_SCHED_BATCHED) {
         const int waves = p->tune_waves > 0 ? p->tune_waves : 4;
         const int blocks = p->tune_blocks > 0 ? p->tune_blocks : std::max(1, c->cus * (16 / std::max(1, waves)));
-        const int refill = p->tune_refill > 0 ? p->tune_refill : 32;
+        const int refill = p->tune_refill > 0 ? p->tune_refill : kDefaultRefill;
         if ((rc = shape_batched(c, P, waves, blocks, refill, p->tune_item_level)) != ARC_OK)
             return rc;
     } else if (p->schedule == ARC_SCHED_BATCHED_TUNED) {
@@ -1001,7 +1008,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
     arc_tune_result best{};
     best.waves = 4;
     best.waves_per_cu = 16;
-    best.refill = 32;
+    best.refill = kDefaultRefill;
     best.item_delta = kDefaultItemDepth;
     double ms_best;
     if ((rc = time_shape(best, &ms_best)) != ARC_OK) return rc;
@@ -1016,9 +1023,12 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
         }
         return ARC_OK;
     };
-    // (1) work-item level (levels below the first; the run clamps it to the memory bound)
+    // (1) work-item level (levels below the first; the run clamps it to the memory bound). Only
+    // levels at or below the default: higher ones win on a source sample, whose subtrees are few,
+    // but on the full run their subtrees outgrow the LDS stacks (1024^3 x 16384 sources, four
+    // levels below the first: 3.8e8 rays spilled and 760 ms against 712 ms at five).
     const arc_tune_result base1 = best;
-    for (int d : {2, 3, 4, 6, 7}) {
+    for (int d : {kDefaultItemDepth + 1, kDefaultItemDepth + 2}) {
         arc_tune_result t = base1;
         t.item_delta = d;
         if ((rc = consider(t)) != ARC_OK) return rc;
@@ -1035,7 +1045,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
         }
     // (3) refill threshold
     const arc_tune_result base3 = best;
-    for (int rf : {8, 16, 48}) {
+    for (int rf : {16, 32, 48, 56}) {
         if (rf == base3.refill) continue;
         arc_tune_result t = base3;
         t.refill = rf;

@@ -514,15 +514,20 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 // are enough independent subtrees), one persistent launch traces every remaining subtree.
 //
 // Each wave keeps 64 rays in flight, one per lane, and advances them up to kSegAhead crossings per
-// iteration. Lanes whose ray ends are refilled (once at least `refill` lanes are idle)
-// from the wave's LDS stack, then from the wave's private spill area, then from the
-// global work queue of subtree roots (one atomic per refill). A splitting lane continues
-// with child 0 and pushes children 1-3. The LDS stack is a ring: when it would overflow,
-// its oldest entries move to the top of the spill area, so the pair behaves as one LIFO
-// stack and the wave works depth first. Waves share nothing but the work-queue head, so
-// each wave ends when the queue is drained and its own stacks are empty.
+// iteration. A splitting lane pushes all four children and goes idle with the lanes whose ray
+// ended; once at least `refill` lanes are idle they are refilled from the wave's LDS stack,
+// then from the wave's private spill area, then from the global work queue of subtree roots
+// (one atomic per refill), and every new ray of the iteration is started in one place. The
+// stack's top holds the children of the latest splits, so the four children of a ray, and the
+// children of rays that split together, enter together and cross the same cells in the same
+// passes: the wave's deposit merge then sums their crossings of a cell into one atomic item
+// (the kernel's throughput is that of the int64 atomics in L2). The LDS stack is a ring: when
+// it would overflow, its oldest entries move to the top of the spill area, so the pair behaves
+// as one LIFO stack and the wave works depth first. Waves share nothing but the work-queue
+// head, so each wave ends when the queue is drained and its own stacks are empty.
 // -------------------------------------------------------------------------------------
-constexpr int kStackCap = 256;  // power of two, >= 3 * 64 children of one split round
+constexpr int kStackCap = 256;  // power of two, >= 4 * 64 children of one split round
+static_assert(kStackCap >= 4 * 64, "a split round of all lanes must fit the ring");
 
 template <int NB, int PREC, int WPB, bool CORR, bool THIN>
 __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
@@ -551,13 +556,51 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
     LaneStats st;
     st.clear();
     for (;;) {
+        // one pass over the lanes that hold a ray
+        int ev = kContinue;
+        if (__any(has)) {
+            if constexpr (CORR)
+                ev = trace_pass_corr<NB, PREC, kSegAheadCorr, THIN>(A, ray, has, st, dep);
+            else
+                ev = trace_pass<NB, PREC, kSegAhead, THIN>(A, ray, has, st, dep);
+        }
+        // splits: the four children go to the stack, child 0 on top
+        const uint64_t sp = __ballot(ev == kSplit);
+        if (sp) {
+            const int need = 4 * __popcll(sp);
+            if (top + need > kStackCap) {
+                // move the oldest entries to the top of the spill area
+                const int m = top + need - kStackCap;
+                for (int i = lane; i < m; i += 64) {
+                    const uint32_t g = nspill + (uint32_t)i;
+                    if (g < spill_cap)
+                        spill[g] = stk[(base + i) & (kStackCap - 1)];
+                    else
+                        atomicAdd(&A.counters[kQueueOverflow], 1ull);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                spilled += (uint32_t)m;
+                nspill = min(spill_cap, nspill + (uint32_t)m);
+                base = (base + m) & (kStackCap - 1);
+                top -= m;
+            }
+            if (ev == kSplit) {
+                const int srank = __popcll(sp & lt);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    stk[(base + top + 4 * srank + (3 - k)) & (kStackCap - 1)] = child_stack<NB>(ray, k);
+            }
+            top += need;
+        }
+        if (ev != kContinue) has = false;
+        // refill of the idle lanes: LDS stack, then spill area, then the work queue
         const uint64_t idle = __ballot(!has);
         const int nidle = __popcll(idle);
         const bool pending = top > 0 || nspill > 0 || !qdone;
+        SRec r;
+        bool got = false;
         if (nidle > 0 && pending && (nidle >= refill || nidle == 64)) {
             const int rank = __popcll(idle & lt);
-            SRec r;
-            bool got = false;
             int take = min(nidle, top);
             if (!has && rank < take) {
                 r = stk[(base + top - 1 - rank) & (kStackCap - 1)];
@@ -598,53 +641,12 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
                     if (b0 + (uint32_t)rem >= n_items) qdone = true;
                 }
             }
-            if (got) {
-                record_tree<NB>(A, r.src, r.lp);
-                has = ray_init<NB, THIN>(A, r, ray, st);
-            }
         }
-        if (!__any(has)) {
-            if (top == 0 && nspill == 0 && qdone) break;
-            continue;
+        if (got) {
+            record_tree<NB>(A, r.src, r.lp);
+            has = ray_init<NB, THIN>(A, r, ray, st);
         }
-        int ev;
-        if constexpr (CORR)
-            ev = trace_pass_corr<NB, PREC, kSegAheadCorr, THIN>(A, ray, has, st, dep);
-        else
-            ev = trace_pass<NB, PREC, kSegAhead, THIN>(A, ray, has, st, dep);
-        const uint64_t sp = __ballot(ev == kSplit);
-        if (sp) {
-            const int need = 3 * __popcll(sp);
-            if (top + need > kStackCap) {
-                // move the oldest entries to the top of the spill area
-                const int m = top + need - kStackCap;
-                for (int i = lane; i < m; i += 64) {
-                    const uint32_t g = nspill + (uint32_t)i;
-                    if (g < spill_cap)
-                        spill[g] = stk[(base + i) & (kStackCap - 1)];
-                    else
-                        atomicAdd(&A.counters[kQueueOverflow], 1ull);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                spilled += (uint32_t)m;
-                nspill = min(spill_cap, nspill + (uint32_t)m);
-                base = (base + m) & (kStackCap - 1);
-                top -= m;
-            }
-            if (ev == kSplit) {
-                const int srank = __popcll(sp & lt);
-#pragma unroll
-                for (int k = 1; k < 4; ++k)
-                    stk[(base + top + 3 * srank + (k - 1)) & (kStackCap - 1)] = child_stack<NB>(ray, k);
-            }
-            top += need;
-            if (ev == kSplit) {
-                const SRec c0 = child_stack<NB>(ray, 0);
-                record_tree<NB>(A, c0.src, c0.lp);
-                has = ray_init<NB, THIN>(A, c0, ray, st);
-            }
-        }
-        if (ev == kTerminate || ev == kEscape) has = false;
+        if (!__any(has) && top == 0 && nspill == 0 && qdone) break;
     }
     flush_stats<NB>(A, st);
     dep.flush(A);

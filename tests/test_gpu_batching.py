@@ -68,7 +68,7 @@ def test_autotuner_shape_matches_plain_bitwise(arc, ctx):
                        rays_per_cell=w.trace["rays_per_cell"], eps_term=w.trace["eps_term"])
     assert res["candidates"] >= 10
     assert res["waves"] in (2, 4, 8) and res["waves_per_cu"] in (8, 12, 16)
-    assert res["refill"] in (8, 16, 32, 48) and 2 <= res["item_delta"] <= 7
+    assert res["refill"] in (16, 32, 48, 56, 64) and 5 <= res["item_delta"] <= 7
     assert 0 < res["ms_best"] <= res["ms_default"]
     tuned = run_gpu_trace(arc, ctx, w, schedule="batched_tuned")
     assert np.array_equal(tuned["J"], plain["J"])
