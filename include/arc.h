@@ -140,9 +140,10 @@ typedef struct {
                               results are identical to 0 */
     int32_t correction;    /* geometric correction (section 2.5), ARC_CORR_*; needs
                               ARC_PREC_FP32_COMP (else ARC_E_UNSUPPORTED) */
-    int32_t spill_cap;     /* batched: ray records of each wave's spill area in device memory
-                              (0 = 4096; < 0 = ARC_E_ARG). Rays that do not fit are dropped and
-                              the call returns ARC_E_QUEUE. */
+    int32_t spill_cap;     /* batched: records of each wave's spill area in device memory, one
+                              per split ray waiting with its four children (0 = 4096; < 0 =
+                              ARC_E_ARG). Records that do not fit are dropped and the call
+                              returns ARC_E_QUEUE. */
 } arc_trace_params;
 
 /* Geometric correction (section 2.5). D_edge: distance from a crossing's midpoint to the
@@ -177,7 +178,8 @@ typedef struct {
     uint64_t splits;       /* rays split into four children */
     uint64_t terminated;   /* rays ended by the attenuation criterion */
     uint64_t escaped_rays; /* rays that left the grid */
-    uint64_t spills;       /* batched: ray records moved from on-chip queues to memory */
+    uint64_t spills;       /* batched: records (a split ray's four children each) moved from
+                              on-chip stacks to memory */
     int64_t tree_count;    /* rays appended to tree_out (may exceed tree_cap) */
     double u_j[4];         /* fixed-point unit of each bin [photons/s * cell] */
     double ms_trace;       /* device time of the trace kernels [ms] */

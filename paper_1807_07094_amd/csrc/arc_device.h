@@ -721,7 +721,7 @@ __device__ __forceinline__ int trace_pass(const TraceArgs& A, Ray<NB>& ray, bool
 }
 
 // trace_pass with the geometric correction: up to K crossings per lane, the neighbours'
-// opacities loaded with the cells'. Two crossings' cells form a window, as without the
+// opacities loaded with the cells'. The crossings' cells form windows, as without the
 // correction; in mode 2 their neighbours' high limbs, then their low limbs, form two more.
 #ifndef ARC_SEG_AHEAD_CORR
 #define ARC_SEG_AHEAD_CORR 4
@@ -731,7 +731,7 @@ template <int NB, int PREC, int K, bool THIN, class Depositor>
 __device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray, bool active, LaneStats& st,
                                                Depositor& deposit)
 {
-    static_assert(kDepWindow == 2, "modes 1 and 3 deposit two crossings per window");
+    static_assert(K % kDepWindow == 0, "whole windows per pass");
     Seg sg[K];
     bool have[K];
     bool go = active;
@@ -762,7 +762,6 @@ __device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray,
     }
     float T[NB], esc[NB];
     ray_transmission<NB, PREC>(ray, T);
-    static_assert(K % 2 == 0, "whole windows per pass");
     Dep<NB> dep[K], dj[K], dm[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
@@ -771,7 +770,7 @@ __device__ __forceinline__ int trace_pass_corr(const TraceArgs& A, Ray<NB>& ray,
             ev = deposit_seg_corr<NB, PREC, THIN>(A, ray, sg[j], kap[j], kapn[j], st, dep[j], dj[j], dm[j], T, esc);
     }
 #pragma unroll
-    for (int j = 0; j < K; j += 2) {
+    for (int j = 0; j < K; j += kDepWindow) {
         deposit.template add<kWhole>(dep + j, A.J, A.nbp);
         if (A.corr == 2) {
             deposit.template add<kWhole>(dj + j, A.J, A.nbp);
@@ -800,18 +799,29 @@ __device__ __forceinline__ RayRec child_rec(const Ray<NB>& ray, int k)
     return r;
 }
 
+// A split ray's family record for the persistent kernel's stacks: the ray's id and optical
+// depth, from which each of its four children is derived when it is taken.
 template <int NB>
-__device__ __forceinline__ StackRec<NB> child_stack(const Ray<NB>& ray, int k)
+__device__ __forceinline__ StackRec<NB> family_rec(const Ray<NB>& ray)
 {
     StackRec<NB> r;
     r.src = ray.src;
-    const uint32_t level = (ray.lp >> kLevelShift) + 1u;
-    r.lp = (level << kLevelShift) | (((ray.lp & kPixMask) << 2) + (uint32_t)k);
+    r.lp = ray.lp;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         r.tau[b] = ray.tau[b];
         r.taulo[b] = ray.taulo[b];
     }
+    return r;
+}
+
+// Child k of the split ray a family record holds (section 2.1 iii c).
+template <int NB>
+__device__ __forceinline__ StackRec<NB> family_child(const StackRec<NB>& f, int k)
+{
+    StackRec<NB> r = f;
+    const uint32_t level = (f.lp >> kLevelShift) + 1u;
+    r.lp = (level << kLevelShift) | (((f.lp & kPixMask) << 2) + (uint32_t)k);
     return r;
 }
 

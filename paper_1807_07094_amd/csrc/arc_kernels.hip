@@ -514,20 +514,21 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 // are enough independent subtrees), one persistent launch traces every remaining subtree.
 //
 // Each wave keeps 64 rays in flight, one per lane, and advances them up to kSegAhead crossings per
-// iteration. A splitting lane pushes all four children and goes idle with the lanes whose ray
-// ended; once at least `refill` lanes are idle they are refilled from the wave's LDS stack,
-// then from the wave's private spill area, then from the global work queue of subtree roots
-// (one atomic per refill), and every new ray of the iteration is started in one place. The
-// stack's top holds the children of the latest splits, so the four children of a ray, and the
-// children of rays that split together, enter together and cross the same cells in the same
-// passes: the wave's deposit merge then sums their crossings of a cell into one atomic item
-// (the kernel's throughput is that of the int64 atomics in L2). The LDS stack is a ring: when
-// it would overflow, its oldest entries move to the top of the spill area, so the pair behaves
-// as one LIFO stack and the wave works depth first. Waves share nothing but the work-queue
-// head, so each wave ends when the queue is drained and its own stacks are empty.
+// iteration. A splitting lane pushes one family record (the ray, from which its four children
+// are derived) and goes idle with the lanes whose ray ended; once at least `refill` lanes are
+// idle they are refilled with whole families from the wave's LDS stack, then from the wave's
+// private spill area, and when both are empty from the global work queue of subtree roots (one
+// atomic per refill); every new ray of the iteration is started in one place. The stack's top
+// holds the latest splits, so the four children of a ray, and the children of rays that split
+// together, enter together and cross the same cells in the same passes: the wave's deposit
+// merge then sums their crossings of a cell into one atomic item (the kernel's throughput is
+// that of the int64 atomics in L2). The LDS stack is a ring: when it would overflow, its
+// oldest entries move to the top of the spill area, so the pair behaves as one LIFO stack and
+// the wave works depth first. Waves share nothing but the work-queue head, so each wave ends
+// when the queue is drained and its own stacks are empty.
 // -------------------------------------------------------------------------------------
-constexpr int kStackCap = 256;  // power of two, >= 4 * 64 children of one split round
-static_assert(kStackCap >= 4 * 64, "a split round of all lanes must fit the ring");
+constexpr int kStackCap = 64;  // family records; power of two, >= 64 splits of one round
+static_assert(kStackCap >= 64, "a split round of all lanes must fit the ring");
 
 template <int NB, int PREC, int WPB, bool CORR, bool THIN>
 __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
@@ -564,10 +565,10 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
             else
                 ev = trace_pass<NB, PREC, kSegAhead, THIN>(A, ray, has, st, dep);
         }
-        // splits: the four children go to the stack, child 0 on top
+        // splits: one family record each
         const uint64_t sp = __ballot(ev == kSplit);
         if (sp) {
-            const int need = 4 * __popcll(sp);
+            const int need = __popcll(sp);
             if (top + need > kStackCap) {
                 // move the oldest entries to the top of the spill area
                 const int m = top + need - kStackCap;
@@ -584,16 +585,12 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
                 base = (base + m) & (kStackCap - 1);
                 top -= m;
             }
-            if (ev == kSplit) {
-                const int srank = __popcll(sp & lt);
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    stk[(base + top + 4 * srank + (3 - k)) & (kStackCap - 1)] = child_stack<NB>(ray, k);
-            }
+            if (ev == kSplit) stk[(base + top + __popcll(sp & lt)) & (kStackCap - 1)] = family_rec<NB>(ray);
             top += need;
         }
         if (ev != kContinue) has = false;
-        // refill of the idle lanes: LDS stack, then spill area, then the work queue
+        // refill of the idle lanes: whole families from the LDS stack, then from the spill
+        // area, then (both empty) single roots from the work queue; four lanes per family
         const uint64_t idle = __ballot(!has);
         const int nidle = __popcll(idle);
         const bool pending = top > 0 || nspill > 0 || !qdone;
@@ -601,25 +598,26 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
         bool got = false;
         if (nidle > 0 && pending && (nidle >= refill || nidle == 64)) {
             const int rank = __popcll(idle & lt);
-            int take = min(nidle, top);
-            if (!has && rank < take) {
-                r = stk[(base + top - 1 - rank) & (kStackCap - 1)];
+            const int fam = min(nidle >> 2, top);
+            if (!has && rank < 4 * fam) {
+                r = family_child<NB>(stk[(base + top - 1 - (rank >> 2)) & (kStackCap - 1)], rank & 3);
                 got = true;
             }
-            top -= take;
-            int rem = nidle - take;
-            if (rem > 0 && nspill > 0) {
-                const int t2 = min(rem, (int)nspill);
+            top -= fam;
+            int used = 4 * fam;
+            const int fam2 = min((nidle - used) >> 2, (int)nspill);
+            if (fam2 > 0) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                if (!has && rank >= take && rank < take + t2) {
-                    r = spill[nspill - 1u - (uint32_t)(rank - take)];
+                if (!has && rank >= used && rank < used + 4 * fam2) {
+                    r = family_child<NB>(spill[nspill - 1u - (uint32_t)((rank - used) >> 2)], (rank - used) & 3);
                     got = true;
                 }
-                nspill -= (uint32_t)t2;
-                take += t2;
-                rem -= t2;
+                nspill -= (uint32_t)fam2;
+                used += 4 * fam2;
             }
-            if (rem > 0 && !qdone) {
+            const int rem = nidle - used;
+            if (rem > 0 && top == 0 && nspill == 0 && !qdone) {
+                const int take = used;
                 uint32_t b0 = 0;
                 if (lane == 0) b0 = atomicAdd(head, (uint32_t)rem);
                 b0 = __shfl(b0, 0, 64);

@@ -117,7 +117,7 @@ def test_chemistry_graph_replays_equal_eager(arc, ctx):
 
 def deep_subtrees():
     # level-1 work items on a 96^3 grid: every item is a whole subtree of up to 8 levels,
-    # far more than a wave's 256-record stack holds
+    # far more than a wave's LDS stack (64 split rays' families) holds
     return W.lognormal(96, 8, 25, source_cells="uniform")
 
 
