@@ -28,12 +28,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Valid for the kernel sources with these digests; with any other sources they are stale and
 # reported as null.
 MEASURED_COUNTERS = {
-    "bytes_per_crossing": 22.15,
-    "valu_per_crossing": 6.625,
-    "l2_hit_rate": 0.085,
+    "bytes_per_crossing": 15.73,
+    "valu_per_crossing": 5.991,
+    "l2_hit_rate": 0.0941,
     "sha256": {
-        "paper_1807_07094_amd/csrc/arc_device.h": "3f6adaa1699be29f42006432c32ccbb829b00e0634b8ec466770313d0fc08d9d",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "44cf5d898ec21227009cf8b93580ce501aacc4d320b3fbfa256ee23f15c77870",
+        "paper_1807_07094_amd/csrc/arc_device.h": "bf4d52d1c448297a7653879377765fccfbd185f9d9d8e1a69f99a62eb7ae1664",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "10f61fb91323858a15e30b91ccd87112655f84c0b5903afc59f8a0ac2fddc894",
     },
     "profile": "profiles/hbm_l2_sq_k_trace_persistent_grf1024_16384src.md",
 }

@@ -561,12 +561,13 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
 // from 1.4e8 to 4e5). Lowered while the larger ray buffer would exceed item_bytes.
 constexpr int kDefaultItemDepth = 5;
 
-// Default refill threshold of the persistent launch: a wave refills only once all its lanes
-// are idle, so that its rays, mostly children of the same splits, start together and their
-// merged deposits make fewer atomics (1024^3 x 16384 sources from the generated state: refill
-// at 32, 48 and 64 idle lanes, 0.283, 0.273 and 0.261 deposit items per crossing, 744, 718 and
-// 712 ms).
-constexpr int kDefaultRefill = 64;
+// Default refill threshold of the persistent launch: a wave refills once 48 of its lanes are
+// idle, so that many rays, mostly children of the same splits, start together and their merged
+// deposits make fewer atomics (1024^3 x 16384 sources from the generated state, merge windows
+// of two segments: refill at 32, 48 and 64 idle lanes, 0.283, 0.273 and 0.261 deposit items per
+// crossing, 744, 718 and 712 ms; windows of four: 48 and 64, 686 and 696 ms, the wider merge
+// costing more issue per crossing than the last atomics it saves).
+constexpr int kDefaultRefill = 48;
 
 // Records of a ray buffer, without keeping its contents.
 hipError_t grow_rays(arc_ctx* c, int i, size_t n)
@@ -1045,7 +1046,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
         }
     // (3) refill threshold
     const arc_tune_result base3 = best;
-    for (int rf : {16, 32, 48, 56}) {
+    for (int rf : {16, 32, 56, 64}) {
         if (rf == base3.refill) continue;
         arc_tune_result t = base3;
         t.refill = rf;

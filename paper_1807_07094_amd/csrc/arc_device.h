@@ -659,15 +659,19 @@ __device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray
 }
 
 // Segments whose geometry is computed ahead of their deposits (opacity loads in flight
-// per lane).
+// per lane), and segments of each lane whose deposits the wave merges together: the merge
+// window of four (256 crossings) fits the LDS of three waves per SIMD beside the family
+// stacks, and the kernel's time follows the atomic items it leaves (1024^3 x 16384 sources:
+// windows of two and ten segments ahead, 0.273 items per crossing and 715 ms; windows of four
+// and eight ahead, 0.236 and 686 ms).
 #ifndef ARC_SEG_AHEAD
-#define ARC_SEG_AHEAD 10
+#define ARC_SEG_AHEAD 8
 #endif
 constexpr int kSegAhead = ARC_SEG_AHEAD;
 #ifndef ARC_DEP_WINDOW
-#define ARC_DEP_WINDOW 2
+#define ARC_DEP_WINDOW 4
 #endif
-constexpr int kDepWindow = ARC_DEP_WINDOW;  // segments of each lane whose deposits are merged together
+constexpr int kDepWindow = ARC_DEP_WINDOW;
 
 // Up to K crossings of one lane per pass: the geometry of K segments is computed first
 // and their opacities are loaded together (K loads in flight per lane), then the
