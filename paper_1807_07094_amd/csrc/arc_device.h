@@ -28,7 +28,9 @@ constexpr uint32_t kNoCell = 0xFFFFFFFFu;
 // line of opacity (and two lines of field) and a block is 8 KB of opacity.
 __host__ __device__ __forceinline__ uint32_t spread3(uint32_t v)
 {
-    return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
+    // bits 0, 1, 2 -> 0, 3, 6: bit 2 moves by 4 first, then bits 1 and 2 by 2
+    const uint32_t x = ((v << 4) | v) & 0x43u;
+    return ((x << 2) | x) & 0x49u;
 }
 __host__ __device__ __forceinline__ uint32_t blocked_index(int x, int y, int z, int nbx8, int nby8)
 {
@@ -116,7 +118,7 @@ constexpr float kTauThin = 0.1f;  // optical depth that bounds the optically thi
 template <int NB>
 struct Ray {
     float e[3];           // |d_i|
-    float ie[3];          // 1 / |d_i| (hardware reciprocal, within 1 ulp), 0 if d_i == 0
+    float ie[3];          // 1 / |d_i| (hardware reciprocal, within 1 ulp), +inf if d_i == 0
     float a[3];           // next-boundary distance along each axis (exact)
     int c[3];             // current cell
     int step[3];          // +1, -1 or 0
@@ -181,11 +183,14 @@ __device__ __forceinline__ int start_index(float xs, float t0, float d)
 // Per-axis terms of blocked_index(): index = term(x, 0) + term(y, 1) + term(z, 2).
 __device__ __forceinline__ uint32_t axis_term(const TraceArgs& A, int i, int v)
 {
-    const uint32_t blk = (uint32_t)(v >> 3) << 9;
+    // grids are at most 2048 cells per axis: the block's first cell index along the axis is
+    // below 2^17 and the blocks it stands for below 2^17; with those ranges stated the multiply
+    // is the full-rate 24-bit one
+    const uint32_t blk9 = ((uint32_t)v << 6) & 0x1FE00u;
     const uint32_t m = spread3((uint32_t)v & 7u) << i;
-    if (i == 0) return blk + m;
-    if (i == 1) return blk * (uint32_t)A.nbx8 + m;
-    return blk * (uint32_t)A.nbx8 * (uint32_t)A.nby8 + m;
+    if (i == 0) return blk9 + m;
+    if (i == 1) return blk9 * ((uint32_t)A.nbx8 & 0x1FFFFu) + m;
+    return blk9 * (((uint32_t)A.nbx8 * (uint32_t)A.nby8) & 0x1FFFFu) + m;
 }
 
 // Non-negative float to the nearest int64 (v < 2^63): two exact 32-bit halves.
@@ -252,7 +257,7 @@ __device__ __forceinline__ bool ray_init(const TraceArgs& A, const Rec& r, Ray<N
         const int c = start_index(xs[i], t0, d[i]);
         ray.c[i] = c;
         ray.e[i] = fabsf(d[i]);
-        ray.ie[i] = d[i] != 0.0f ? __builtin_amdgcn_rcpf(ray.e[i]) : 0.0f;
+        ray.ie[i] = d[i] != 0.0f ? __builtin_amdgcn_rcpf(ray.e[i]) : INFINITY;
         ray.step[i] = d[i] > 0.0f ? 1 : (d[i] < 0.0f ? -1 : 0);
         // d_i = 0: the distance to the upper face (no boundary is met along this axis; the
         // geometric correction reads the position from it)
@@ -377,32 +382,38 @@ template <int NB, int PREC, bool CORR = false>
 __device__ __forceinline__ Seg geom_next(const TraceArgs& A, Ray<NB>& ray)
 {
     constexpr float kNear = 1.000001f;
-    const float t0 = ray.e[0] > 0.0f ? ray.a[0] * ray.ie[0] : INFINITY;
-    const float t1 = ray.e[1] > 0.0f ? ray.a[1] * ray.ie[1] : INFINITY;
-    const float t2 = ray.e[2] > 0.0f ? ray.a[2] * ray.ie[2] : INFINITY;
-    int w = t1 < t0 ? 1 : 0;
-    float tw = w ? t1 : t0;
-    if (t2 < tw) {
-        w = 2;
-        tw = t2;
-    }
-    int mask = 1 << w;
+    // a_i > 0 always, and ie_i = +inf where d_i = 0, so those axes give t_i = +inf
+    const float t0 = ray.a[0] * ray.ie[0];
+    const float t1 = ray.a[1] * ray.ie[1];
+    const float t2 = ray.a[2] * ray.ie[2];
+    // the selects follow the comparisons themselves, not an axis number (a select chain on
+    // w == 0, w == 1 is turned into an indexed access to the ray, which lives in scratch)
+    const bool b1 = t1 < t0;
+    float tw = b1 ? t1 : t0;
+    float aw = b1 ? ray.a[1] : ray.a[0];
+    float ew = b1 ? ray.e[1] : ray.e[0];
+    float iew = b1 ? ray.ie[1] : ray.ie[0];
+    const bool b2 = t2 < tw;
+    tw = b2 ? t2 : tw;
+    aw = b2 ? ray.a[2] : aw;
+    ew = b2 ? ray.e[2] : ew;
+    iew = b2 ? ray.ie[2] : iew;
+    int w = b2 ? 2 : (b1 ? 1 : 0);
+    int mask = b2 ? 4 : (b1 ? 2 : 1);
     bool at_end;
-    float aw = w == 0 ? ray.a[0] : (w == 1 ? ray.a[1] : ray.a[2]);
-    float ew = w == 0 ? ray.e[0] : (w == 1 ? ray.e[1] : ray.e[2]);
-    float iew = w == 0 ? ray.ie[0] : (w == 1 ? ray.ie[1] : ray.ie[2]);
     if constexpr (PREC == 0) {
         const bool near = (w != 0 && t0 <= tw * kNear) || (w != 1 && t1 <= tw * kNear) || (w != 2 && t2 <= tw * kNear);
         if (near) {
             // exact argmin and ties: t_i < t_j  <=>  a_i e_j < a_j e_i
             int ww = -1;
-            float ab = 0.0f, eb = 0.0f;
+            float ab = 0.0f, eb = 0.0f, ib = 0.0f;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 if (ray.e[i] > 0.0f && (ww < 0 || cmp_prod(ray.a[i], eb, ab, ray.e[i]) < 0)) {
                     ww = i;
                     ab = ray.a[i];
                     eb = ray.e[i];
+                    ib = ray.ie[i];
                 }
             }
             w = ww;
@@ -412,7 +423,7 @@ __device__ __forceinline__ Seg geom_next(const TraceArgs& A, Ray<NB>& ray)
                 if (ray.e[i] > 0.0f && cmp_prod(ray.a[i], eb, ab, ray.e[i]) == 0) mask |= 1 << i;
             aw = ab;
             ew = eb;
-            iew = w == 0 ? ray.ie[0] : (w == 1 ? ray.ie[1] : ray.ie[2]);
+            iew = ib;
             tw = aw * iew;
         }
         if (ray.tend > tw * kNear)
