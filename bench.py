@@ -28,11 +28,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Valid for the kernel sources with these digests; with any other sources they are stale and
 # reported as null.
 MEASURED_COUNTERS = {
-    "bytes_per_crossing": 15.73,
-    "valu_per_crossing": 5.991,
-    "l2_hit_rate": 0.0941,
+    "bytes_per_crossing": 15.72,
+    "valu_per_crossing": 5.832,
+    "l2_hit_rate": 0.0943,
     "sha256": {
-        "paper_1807_07094_amd/csrc/arc_device.h": "bf4d52d1c448297a7653879377765fccfbd185f9d9d8e1a69f99a62eb7ae1664",
+        "paper_1807_07094_amd/csrc/arc_device.h": "bdb15bc8cf3471f763d07b2d97f875bb5f0df04c4efdf0ebe8721b2ef88d84c1",
         "paper_1807_07094_amd/csrc/arc_kernels.hip": "10f61fb91323858a15e30b91ccd87112655f84c0b5903afc59f8a0ac2fddc894",
     },
     "profile": "profiles/hbm_l2_sq_k_trace_persistent_grf1024_16384src.md",
