@@ -662,8 +662,10 @@ hipError_t enqueue_levels(const TracePlan& P, hipStream_t st)
         uint32_t* cout = cnt + ((l - P.A.level0 + 1) & 1);
         if ((e = launch_set_u32(cout, 0u, st)) != hipSuccess) return e;
         const uint32_t out_cap = (uint32_t)std::min<size_t>(P.cap[1 - cur], 0xFFFFFFF0u);
-        if ((e = launch_trace_rays(P.A, P.precision, r[cur], cin, (uint32_t)bound, r[1 - cur], cout, out_cap, st)) !=
-            hipSuccess)
+        // the last level leaves family records: the work items of the persistent launch
+        const int fam_out = l + 1 == P.litem ? 1 : 0;
+        if ((e = launch_trace_rays(P.A, P.precision, r[cur], cin, (uint32_t)bound, r[1 - cur], cout, out_cap, fam_out,
+                                   st)) != hipSuccess)
             return e;
         bound *= 4;
         cur = 1 - cur;
@@ -677,8 +679,10 @@ hipError_t enqueue_persistent(const TracePlan& P, hipStream_t st)
 {
     if (P.nsrc == 0) return hipSuccess;
     const int cur = (P.litem - P.A.level0) & 1;
+    // above the first level the work items are the family records of the level before
+    const int fam = P.litem > P.A.level0 ? 1 : 0;
     return launch_trace_persistent(P.A, P.precision, cur ? P.rays1 : P.rays0, P.u32 + 2 + cur, P.u32 + 1, P.spill,
-                                   P.spill_cap, P.blocks, P.waves, P.refill, st);
+                                   P.spill_cap, P.blocks, P.waves, P.refill, fam, st);
 }
 
 // Stage 3: rates (eq:ion per absorber, section 2.8 heating) and the absorbed ledger.
@@ -715,7 +719,7 @@ arc_status run_plain(arc_ctx* c, const TracePlan& P, hipStream_t st)
             }
             HIP_TRY(c, launch_set_u32(c->u32, 0u, st));
             HIP_TRY(c, launch_trace_rays(P.A, P.precision, c->rays[cur], nullptr, (uint32_t)n, c->rays[1 - cur], c->u32,
-                                         (uint32_t)std::min<size_t>(c->rcap[1 - cur], 0xFFFFFFF0u), st));
+                                         (uint32_t)std::min<size_t>(c->rcap[1 - cur], 0xFFFFFFF0u), 0, st));
             uint32_t nn = 0;
             HIP_TRY(c, hipMemcpyAsync(&nn, c->u32, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             HIP_TRY(c, hipStreamSynchronize(st));

@@ -814,6 +814,23 @@ __device__ __forceinline__ RayRec child_rec(const Ray<NB>& ray, int k)
     return r;
 }
 
+// A split ray's family record in memory (the persistent kernel's work items): the ray's id
+// and optical depth, from which each of its four children is derived when it is taken.
+template <int NB>
+__device__ __forceinline__ RayRec family_item(const Ray<NB>& ray)
+{
+    RayRec r;
+    r.src = ray.src;
+    r.lp = ray.lp;
+    r.pad0 = r.pad1 = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        r.tau[b] = b < NB ? ray.tau[b] : 0.0f;
+        r.taulo[b] = b < NB ? ray.taulo[b] : 0.0f;
+    }
+    return r;
+}
+
 // A split ray's family record for the persistent kernel's stacks: the ray's id and optical
 // depth, from which each of its four children is derived when it is taken.
 template <int NB>

@@ -83,11 +83,14 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, const uint32_t* order, RayRec* out,
                              hipStream_t s);
 // n_in_dev (optional) holds the ray count on the device; n_in bounds it and sizes the grid.
+// fam_out: a split ray writes one family record (its own id and depth) instead of its four
+// children, for the persistent launch.
 hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, const uint32_t* n_in_dev, uint32_t n_in,
-                             RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s);
+                             RayRec* out, uint32_t* n_out, uint32_t out_cap, int fam_out, hipStream_t s);
+// fam: the work items are family records (four rays each), else single rays.
 hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
                                    uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
-                                   int refill, hipStream_t s);
+                                   int refill, int fam, hipStream_t s);
 int persistent_max_waves();
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_probe_deposits(unsigned long long* J, int nbp, int nb, uint64_t ncell, uint64_t items,

@@ -426,7 +426,8 @@ hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, cons
 template <int NB, int PREC, bool CORR, bool THIN>
 __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* __restrict__ in,
                                                     const uint32_t* n_in_dev, uint32_t n_in_host,
-                                                    RayRec* __restrict__ out, uint32_t* n_out, uint32_t out_cap)
+                                                    RayRec* __restrict__ out, uint32_t* n_out, uint32_t out_cap,
+                                                    int fam_out)
 {
     const uint32_t n_in = n_in_dev ? *n_in_dev : n_in_host;
     __shared__ DepScratch<NB> dscr[4];
@@ -458,17 +459,24 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
                 act = false;
             }
         }
+        // a split ray leaves its four children, or (fam_out: the persistent launch's work
+        // items) one family record from which they are derived
         const uint64_t m = __ballot(ev == kSplit);
         if (m) {
+            const uint32_t per = fam_out ? 1u : 4u;
             const int leader = __ffsll((unsigned long long)m) - 1;
             uint32_t wbase = 0;
-            if (lane == leader) wbase = atomicAdd(n_out, 4u * (uint32_t)__popcll(m));
+            if (lane == leader) wbase = atomicAdd(n_out, per * (uint32_t)__popcll(m));
             wbase = __shfl(wbase, leader, 64);
             if (ev == kSplit) {
-                const uint32_t slot = wbase + 4u * (uint32_t)__popcll(m & lt);
-                if (slot + 4u <= out_cap) {
+                const uint32_t slot = wbase + per * (uint32_t)__popcll(m & lt);
+                if (slot + per <= out_cap) {
+                    if (fam_out) {
+                        out[slot] = family_item<NB>(ray);
+                    } else {
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) out[slot + k] = child_rec<NB>(ray, k);
+                        for (int k = 0; k < 4; ++k) out[slot + k] = child_rec<NB>(ray, k);
+                    }
                 } else {
                     atomicAdd(&A.counters[kQueueOverflow], 1ull);
                 }
@@ -481,31 +489,32 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
 
 template <int NB>
 static hipError_t trace_rays_nb(const TraceArgs& A, int prec, const RayRec* in, const uint32_t* n_in_dev,
-                                uint32_t n_in, RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s)
+                                uint32_t n_in, RayRec* out, uint32_t* n_out, uint32_t out_cap, int fam_out,
+                                hipStream_t s)
 {
     const unsigned g = grid_for(n_in, 256, 1u << 16);
     const bool thin = A.r_out != nullptr;
     if (prec == 0 && A.corr && thin)
-        k_trace_rays<NB, 0, true, true><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+        k_trace_rays<NB, 0, true, true><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap, fam_out);
     else if (prec == 0 && A.corr)
-        k_trace_rays<NB, 0, true, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+        k_trace_rays<NB, 0, true, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap, fam_out);
     else if (prec == 0 && thin)
-        k_trace_rays<NB, 0, false, true><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+        k_trace_rays<NB, 0, false, true><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap, fam_out);
     else if (prec == 0)
-        k_trace_rays<NB, 0, false, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+        k_trace_rays<NB, 0, false, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap, fam_out);
     else
-        k_trace_rays<NB, 1, false, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap);
+        k_trace_rays<NB, 1, false, false><<<g, 256, 0, s>>>(A, in, n_in_dev, n_in, out, n_out, out_cap, fam_out);
     return hipGetLastError();
 }
 
 hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, const uint32_t* n_in_dev, uint32_t n_in,
-                             RayRec* out, uint32_t* n_out, uint32_t out_cap, hipStream_t s)
+                             RayRec* out, uint32_t* n_out, uint32_t out_cap, int fam_out, hipStream_t s)
 {
     switch (A.nb) {
-        case 1: return trace_rays_nb<1>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, s);
-        case 2: return trace_rays_nb<2>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, s);
-        case 3: return trace_rays_nb<3>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, s);
-        default: return trace_rays_nb<4>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, s);
+        case 1: return trace_rays_nb<1>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, fam_out, s);
+        case 2: return trace_rays_nb<2>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, fam_out, s);
+        case 3: return trace_rays_nb<3>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, fam_out, s);
+        default: return trace_rays_nb<4>(A, prec, in, n_in_dev, n_in, out, n_out, out_cap, fam_out, s);
     }
 }
 
@@ -534,7 +543,7 @@ template <int NB, int PREC, int WPB, bool CORR, bool THIN>
 __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
                                                                const uint32_t* n_items_dev, uint32_t* head,
                                                                RayRec* __restrict__ spill_all, uint32_t spill_cap,
-                                                               int refill)
+                                                               int refill, int fam)
 {
     using SRec = StackRec<NB>;
     __shared__ SRec lds[WPB * kStackCap];
@@ -598,13 +607,13 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
         bool got = false;
         if (nidle > 0 && pending && (nidle >= refill || nidle == 64)) {
             const int rank = __popcll(idle & lt);
-            const int fam = min(nidle >> 2, top);
-            if (!has && rank < 4 * fam) {
+            const int nfam = min(nidle >> 2, top);
+            if (!has && rank < 4 * nfam) {
                 r = family_child<NB>(stk[(base + top - 1 - (rank >> 2)) & (kStackCap - 1)], rank & 3);
                 got = true;
             }
-            top -= fam;
-            int used = 4 * fam;
+            top -= nfam;
+            int used = 4 * nfam;
             const int fam2 = min((nidle - used) >> 2, (int)nspill);
             if (fam2 > 0) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -615,18 +624,22 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
                 nspill -= (uint32_t)fam2;
                 used += 4 * fam2;
             }
+            // work items: single rays, or (fam) family records taken whole, four lanes each
             const int rem = nidle - used;
-            if (rem > 0 && top == 0 && nspill == 0 && !qdone) {
+            const uint32_t want = fam ? (uint32_t)(rem >> 2) : (uint32_t)rem;
+            if (want > 0 && top == 0 && nspill == 0 && !qdone) {
                 const int take = used;
                 uint32_t b0 = 0;
-                if (lane == 0) b0 = atomicAdd(head, (uint32_t)rem);
+                if (lane == 0) b0 = atomicAdd(head, want);
                 b0 = __shfl(b0, 0, 64);
                 if (b0 >= n_items) {
                     qdone = true;
                 } else {
-                    const uint32_t avail = min((uint32_t)rem, n_items - b0);
-                    if (!has && rank >= take && rank < take + (int)avail) {
-                        const RayRec& it = items[b0 + (uint32_t)(rank - take)];
+                    const uint32_t avail = min(want, n_items - b0);
+                    const int lanes = fam ? 4 * (int)avail : (int)avail;
+                    if (!has && rank >= take && rank < take + lanes) {
+                        const int q = rank - take;
+                        const RayRec& it = items[b0 + (uint32_t)(fam ? q >> 2 : q)];
                         r.src = it.src;
                         r.lp = it.lp;
 #pragma unroll
@@ -634,9 +647,10 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
                             r.tau[b] = it.tau[b];
                             r.taulo[b] = it.taulo[b];
                         }
+                        if (fam) r = family_child<NB>(r, q & 3);
                         got = true;
                     }
-                    if (b0 + (uint32_t)rem >= n_items) qdone = true;
+                    if (b0 + want >= n_items) qdone = true;
                 }
             }
         }
@@ -662,18 +676,19 @@ constexpr size_t kLdsPerCu = 163840;
 
 template <int NB, int PREC, bool CORR, bool THIN>
 static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const uint32_t* n_items, uint32_t* head,
-                                RayRec* spill, uint32_t spill_cap, int blocks, int waves, int refill, hipStream_t s)
+                                RayRec* spill, uint32_t spill_cap, int blocks, int waves, int refill, int fam,
+                                hipStream_t s)
 {
     switch (waves) {
-        case 1: k_trace_persistent<NB, PREC, 1, CORR, THIN><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        case 2: k_trace_persistent<NB, PREC, 2, CORR, THIN><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
-        case 4: k_trace_persistent<NB, PREC, 4, CORR, THIN><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill); break;
+        case 1: k_trace_persistent<NB, PREC, 1, CORR, THIN><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam); break;
+        case 2: k_trace_persistent<NB, PREC, 2, CORR, THIN><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam); break;
+        case 4: k_trace_persistent<NB, PREC, 4, CORR, THIN><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam); break;
         default:
             // eight waves only where their LDS fits a compute unit (else four, in twice the blocks)
             if constexpr (persistent_lds_bytes<NB, 8>() <= kLdsPerCu)
-                k_trace_persistent<NB, PREC, 8, CORR, THIN><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill);
+                k_trace_persistent<NB, PREC, 8, CORR, THIN><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam);
             else
-                k_trace_persistent<NB, PREC, 4, CORR, THIN><<<2 * blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill);
+                k_trace_persistent<NB, PREC, 4, CORR, THIN><<<2 * blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam);
             break;
     }
     return hipGetLastError();
@@ -682,25 +697,25 @@ static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const u
 template <int NB>
 static hipError_t persistent_variant(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
                                      uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
-                                     int refill, hipStream_t s)
+                                     int refill, int fam, hipStream_t s)
 {
     const bool thin = A.r_out != nullptr;
-    if (prec != 0) return persistent_nb<NB, 1, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
-    if (A.corr && thin) return persistent_nb<NB, 0, true, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
-    if (A.corr) return persistent_nb<NB, 0, true, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
-    if (thin) return persistent_nb<NB, 0, false, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
-    return persistent_nb<NB, 0, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+    if (prec != 0) return persistent_nb<NB, 1, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+    if (A.corr && thin) return persistent_nb<NB, 0, true, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+    if (A.corr) return persistent_nb<NB, 0, true, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+    if (thin) return persistent_nb<NB, 0, false, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+    return persistent_nb<NB, 0, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
 }
 
 hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
                                    uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
-                                   int refill, hipStream_t s)
+                                   int refill, int fam, hipStream_t s)
 {
     switch (A.nb) {
-        case 1: return persistent_variant<1>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
-        case 2: return persistent_variant<2>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
-        case 3: return persistent_variant<3>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
-        default: return persistent_variant<4>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, s);
+        case 1: return persistent_variant<1>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+        case 2: return persistent_variant<2>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+        case 3: return persistent_variant<3>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+        default: return persistent_variant<4>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
     }
 }
 

@@ -146,3 +146,16 @@ def test_spill_area_overflow_is_reported_and_context_reused(arc, ctx):
     with pytest.raises(arc.ArcError) as e:
         run_gpu_trace(arc, ctx, w, schedule="batched", spill_cap=-1)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("delta", [0, 1, 3, 5, 6])
+def test_every_work_item_level_equals_plain_bitwise(arc, ctx, delta):
+    """The persistent launch's work items are the first level's rays (delta 0) or the family
+    records the level-synchronous stage leaves (four rays each): every item level gives the
+    plain schedule's field, rays and crossings."""
+    w = W.lognormal(40, 12, 22)
+    p = run_gpu_trace(arc, ctx, w, schedule="plain")
+    b = run_gpu_trace(arc, ctx, w, schedule="batched", tune_item_level=w.trace["level0"] + delta)
+    assert np.array_equal(b["J"], p["J"])
+    assert b["ledger"]["rays"] == p["ledger"]["rays"]
+    assert b["ledger"]["crossings"] == p["ledger"]["crossings"]
