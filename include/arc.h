@@ -144,6 +144,8 @@ typedef struct {
                               per split ray waiting with its four children (0 = 4096; < 0 =
                               ARC_E_ARG). Records that do not fit are dropped and the call
                               returns ARC_E_QUEUE. */
+    int32_t tune_stack;    /* batched: split rays each wave's LDS stack holds before it spills
+                              to memory: 64, 128 or 256 (0 = 64; else ARC_E_ARG) */
 } arc_trace_params;
 
 /* Geometric correction (section 2.5). D_edge: distance from a crossing's midpoint to the
@@ -211,12 +213,14 @@ typedef struct {
     double ms_best;        /* trace time of the chosen shape [ms] (tuning sources) */
     double ms_default;     /* trace time of the default shape [ms] (tuning sources) */
     int32_t candidates;    /* shapes timed */
+    int32_t stack;         /* split rays per wave's LDS stack (64, 128, 256) */
 } arc_tune_result;
 
 /* Autotuner of the batched schedule (no paper counterpart: the paper traces one source
  * at a time). Times launch shapes of the batched tracer on the given sources (pass a
  * representative subset: every shape traces them all, twice) by coordinate descent over
- * the work-item level, waves per workgroup and per CU, and the refill threshold. Every
+ * the work-item level, waves per workgroup and per CU, the refill threshold and the depth
+ * of the waves' LDS stacks. Every
  * shape's fixed-point field is checked against the first one's bit for bit (two 64-bit
  * checksums); a difference returns ARC_E_MISMATCH. The best shape is cached in the context
  * for this grid size, bin count, level range and precision, where ARC_SCHED_BATCHED_TUNED

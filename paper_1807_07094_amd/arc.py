@@ -52,13 +52,13 @@ class TraceParams(C.Structure):
                 ("stream", C.c_void_p), ("tune_waves", C.c_int32), ("tune_blocks", C.c_int32),
                 ("tune_refill", C.c_int32), ("tune_item_level", C.c_int32), ("tree_out", C.c_void_p),
                 ("tree_cap", C.c_int64), ("u_j_override", C.c_double), ("graph", C.c_int32),
-                ("correction", C.c_int32), ("spill_cap", C.c_int32)]
+                ("correction", C.c_int32), ("spill_cap", C.c_int32), ("tune_stack", C.c_int32)]
 
 
 class TuneResult(C.Structure):
     _fields_ = [("waves", C.c_int32), ("waves_per_cu", C.c_int32), ("refill", C.c_int32),
                 ("item_delta", C.c_int32), ("ms_best", C.c_double), ("ms_default", C.c_double),
-                ("candidates", C.c_int32)]
+                ("candidates", C.c_int32), ("stack", C.c_int32)]
 
 
 class Rates(C.Structure):
@@ -215,7 +215,7 @@ class Context:
     @staticmethod
     def _trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term, precision, schedule, stream,
                     tree, tune_waves, tune_blocks, tune_refill, tune_item_level, u_j_override, graph, correction=0,
-                    spill_cap=0):
+                    spill_cap=0, tune_stack=0):
         g = _grid(grid)
         pos = np.ascontiguousarray(sources["pos"], np.float64).reshape(-1, 3)
         ndot = np.ascontiguousarray(sources["ndot"], np.float64).reshape(-1)
@@ -240,20 +240,22 @@ class Context:
                         SCHED[schedule] if isinstance(schedule, str) else int(schedule), _stream(stream),
                         int(tune_waves), int(tune_blocks), int(tune_refill), int(tune_item_level), _ptr(tree),
                         int(tree.numel()) if tree is not None else 0, float(u_j_override), int(bool(graph)),
-                        CORR[correction] if isinstance(correction, str) else int(correction), int(spill_cap))
+                        CORR[correction] if isinstance(correction, str) else int(correction), int(spill_cap),
+                        int(tune_stack))
         # the host arrays must outlive the call: keep them with the structures
         return g, s, b, p, (pos, ndot, frac, e, sig, thr, r_thin, r_out)
 
     def trace(self, grid, sources: dict, bins: dict, dt: float, gamma, heat, level0=1, rays_per_cell=4.0,
               max_level=-1, eps_term=1e-6, precision="fp32_comp", schedule="batched", stream=None, tree=None,
               tune_waves=0, tune_blocks=0, tune_refill=0, tune_item_level=0, u_j_override=0.0, graph=False,
-              correction="none", spill_cap=0) -> dict:
+              correction="none", spill_cap=0, tune_stack=0) -> dict:
         """arc_trace. gamma/heat: device float32 tensors of shape [3, nz, ny, nx]. correction:
         "none", "fc", "conserving" or "fc_squared" (section 2.5). sources may carry "r_thin" and
         "r_thin_out" (section 2.6)."""
         g, s, b, p, _keep = self._trace_args(grid, sources, bins, level0, rays_per_cell, max_level, eps_term,
                                              precision, schedule, stream, tree, tune_waves, tune_blocks, tune_refill,
-                                             tune_item_level, u_j_override, graph, correction, spill_cap)
+                                             tune_item_level, u_j_override, graph, correction, spill_cap,
+                                             tune_stack)
         r = Rates(_ptr(gamma), _ptr(heat))
         led = Ledger()
         self._check(lib().arc_trace(self._h, C.byref(g), C.byref(s), C.byref(b), float(dt), C.byref(p),

@@ -315,6 +315,7 @@ struct TracePlan {
     int precision;
     // batched schedule
     int waves, blocks, refill, litem;
+    int stack;          // split rays per wave's LDS stack
     int spill_cap_req;  // records of each wave's spill area (0: 4096)
     double n_roots;
     size_t cap[2];  // records of rays0 / rays1
@@ -353,6 +354,8 @@ arc_status plan_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const
     if (p->correction != ARC_CORR_NONE && p->precision != ARC_PREC_FP32_COMP)
         return fail(c, ARC_E_UNSUPPORTED, "the geometric correction needs ARC_PREC_FP32_COMP");
     if (p->spill_cap < 0) return fail(c, ARC_E_ARG, "spill_cap must be >= 0");
+    if (p->tune_stack != 0 && p->tune_stack != 64 && p->tune_stack != 128 && p->tune_stack != 256)
+        return fail(c, ARC_E_ARG, "tune_stack must be 0, 64, 128 or 256");
     // optically thin approximation (section 2.6): per-source start radii and/or the measured
     // R_tau<0.1
     bool thin = s->r_thin_out != nullptr;
@@ -569,6 +572,10 @@ constexpr int kDefaultItemDepth = 5;
 // costing more issue per crossing than the last atomics it saves).
 constexpr int kDefaultRefill = 48;
 
+// Default depth of each wave's LDS stack: 64 split rays (2 KB), a full split round of the
+// wave; deeper stacks spill less but hold fewer waves per compute unit.
+constexpr int kDefaultStack = 64;
+
 // Records of a ray buffer, without keeping its contents.
 hipError_t grow_rays(arc_ctx* c, int i, size_t n)
 {
@@ -581,8 +588,9 @@ hipError_t grow_rays(arc_ctx* c, int i, size_t n)
 // Launch shape of the batched schedule and the buffers it needs. item_level: the HEALPix
 // level whose rays are the persistent launch's work items (0: the default depth); it is
 // clamped to [level0, lmax] and to the memory bound.
-arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int refill, int item_level)
+arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int refill, int item_level, int stack)
 {
+    if (stack != 64 && stack != 128 && stack != 256) return fail(c, ARC_E_ARG, "LDS stack depth must be 64, 128 or 256");
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(c, ARC_E_ARG, "tune_waves must be 1, 2, 4 or 8");
     if (blocks < 1) return fail(c, ARC_E_ARG, "tune_blocks must be >= 1");
     const int level0 = P.A.level0, lmax = P.lmax;
@@ -612,6 +620,7 @@ arc_status shape_batched(arc_ctx* c, TracePlan& P, int waves, int blocks, int re
     P.waves = waves;
     P.blocks = blocks;
     P.refill = std::max(1, std::min(64, refill));
+    P.stack = stack;
     P.litem = litem;
     P.n_roots = n_roots;
     P.cap[0] = c->rcap[0];
@@ -682,7 +691,7 @@ hipError_t enqueue_persistent(const TracePlan& P, hipStream_t st)
     // above the first level the work items are the family records of the level before
     const int fam = P.litem > P.A.level0 ? 1 : 0;
     return launch_trace_persistent(P.A, P.precision, cur ? P.rays1 : P.rays0, P.u32 + 2 + cur, P.u32 + 1, P.spill,
-                                   P.spill_cap, P.blocks, P.waves, P.refill, fam, st);
+                                   P.spill_cap, P.blocks, P.waves, P.refill, fam, P.stack, st);
 }
 
 // Stage 3: rates (eq:ion per absorber, section 2.8 heating) and the absorbed ledger.
@@ -921,7 +930,8 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
         const int waves = p->tune_waves > 0 ? p->tune_waves : 4;
         const int blocks = p->tune_blocks > 0 ? p->tune_blocks : std::max(1, c->cus * (16 / std::max(1, waves)));
         const int refill = p->tune_refill > 0 ? p->tune_refill : kDefaultRefill;
-        if ((rc = shape_batched(c, P, waves, blocks, refill, p->tune_item_level)) != ARC_OK)
+        const int stack = p->tune_stack > 0 ? p->tune_stack : kDefaultStack;
+        if ((rc = shape_batched(c, P, waves, blocks, refill, p->tune_item_level, stack)) != ARC_OK)
             return rc;
     } else if (p->schedule == ARC_SCHED_BATCHED_TUNED) {
         const arc_tune_result* t = find_tuned(c, g, P);
@@ -943,7 +953,8 @@ arc_status arc_trace(arc_ctx* c, const arc_grid* g, const arc_sources* s, const 
             if ((rc = plan_trace(c, g, s, b, dt, p, out, P)) != ARC_OK) return rc;
         }
         const int blocks = std::max(1, c->cus * t->waves_per_cu / t->waves);
-        if ((rc = shape_batched(c, P, t->waves, blocks, t->refill, P.A.level0 + t->item_delta)) != ARC_OK) return rc;
+        if ((rc = shape_batched(c, P, t->waves, blocks, t->refill, P.A.level0 + t->item_delta, t->stack)) != ARC_OK)
+            return rc;
     }
     return run_trace(c, P, s, dt, p->schedule, p->graph != 0, st, ledger);
 }
@@ -982,7 +993,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
     // time one shape twice; check its field against the first shape's
     auto time_shape = [&](const arc_tune_result& t, double* ms_out) -> arc_status {
         const int blocks = std::max(1, c->cus * t.waves_per_cu / t.waves);
-        arc_status r2 = shape_batched(c, P, t.waves, blocks, t.refill, P.A.level0 + t.item_delta);
+        arc_status r2 = shape_batched(c, P, t.waves, blocks, t.refill, P.A.level0 + t.item_delta, t.stack);
         if (r2 != ARC_OK) return r2;
         double best = INFINITY;
         for (int rep = 0; rep < 2; ++rep) {
@@ -1003,8 +1014,8 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
             have_ref = true;
         } else if (h[0] != ref[0] || h[1] != ref[1]) {
             return fail(c, ARC_E_MISMATCH,
-                        "launch shape (waves %d, waves/CU %d, refill %d, item delta %d) changed the field",
-                        t.waves, t.waves_per_cu, t.refill, t.item_delta);
+                        "launch shape (waves %d, waves/CU %d, refill %d, item delta %d, stack %d) changed the field",
+                        t.waves, t.waves_per_cu, t.refill, t.item_delta, t.stack);
         }
         ++ncand;
         *ms_out = best;
@@ -1014,6 +1025,7 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
     best.waves = 4;
     best.waves_per_cu = 16;
     best.refill = kDefaultRefill;
+    best.stack = kDefaultStack;
     best.item_delta = kDefaultItemDepth;
     double ms_best;
     if ((rc = time_shape(best, &ms_best)) != ARC_OK) return rc;
@@ -1054,6 +1066,13 @@ arc_status autotune_impl(arc_ctx* c, const arc_grid* g, const arc_sources* s, co
         if (rf == base3.refill) continue;
         arc_tune_result t = base3;
         t.refill = rf;
+        if ((rc = consider(t)) != ARC_OK) return rc;
+    }
+    // (4) depth of the waves' LDS stacks
+    const arc_tune_result base4 = best;
+    for (int sd : {128, 256}) {
+        arc_tune_result t = base4;
+        t.stack = sd;
         if ((rc = consider(t)) != ARC_OK) return rc;
     }
     best.ms_best = ms_best;

@@ -87,10 +87,11 @@ hipError_t launch_seed_roots(uint32_t first_src, uint32_t nsrc, int level0, cons
 // children, for the persistent launch.
 hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, const uint32_t* n_in_dev, uint32_t n_in,
                              RayRec* out, uint32_t* n_out, uint32_t out_cap, int fam_out, hipStream_t s);
-// fam: the work items are family records (four rays each), else single rays.
+// fam: the work items are family records (four rays each), else single rays. stack_cap:
+// split rays each wave's LDS stack holds (64, 128 or 256).
 hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
                                    uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
-                                   int refill, int fam, hipStream_t s);
+                                   int refill, int fam, int stack_cap, hipStream_t s);
 int persistent_max_waves();
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_probe_deposits(unsigned long long* J, int nbp, int nb, uint64_t ncell, uint64_t items,

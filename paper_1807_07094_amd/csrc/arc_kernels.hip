@@ -536,23 +536,26 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 // the wave works depth first. Waves share nothing but the work-queue head, so each wave ends
 // when the queue is drained and its own stacks are empty.
 // -------------------------------------------------------------------------------------
-constexpr int kStackCap = 64;  // family records; power of two, >= 64 splits of one round
-static_assert(kStackCap >= 64, "a split round of all lanes must fit the ring");
+// The stacks live in dynamic LDS: stack_cap family records per wave, a power of two of at
+// least 64 (a split round of all lanes must fit the ring), chosen at launch (the autotuner's
+// LDS stack depth).
+extern __shared__ __align__(16) unsigned char arc_stack_lds[];
 
 template <int NB, int PREC, int WPB, bool CORR, bool THIN>
 __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(TraceArgs A, const RayRec* __restrict__ items,
                                                                const uint32_t* n_items_dev, uint32_t* head,
                                                                RayRec* __restrict__ spill_all, uint32_t spill_cap,
-                                                               int refill, int fam)
+                                                               int refill, int fam, int stack_cap)
 {
     using SRec = StackRec<NB>;
-    __shared__ SRec lds[WPB * kStackCap];
+    SRec* lds = reinterpret_cast<SRec*>(arc_stack_lds);
+    const int cmask = stack_cap - 1;
     __shared__ DepScratch<NB> dscr[WPB];
     const int wid = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint64_t lt = __lanemask_lt();
     const uint32_t n_items = *n_items_dev;
-    SRec* stk = lds + wid * kStackCap;
+    SRec* stk = lds + wid * stack_cap;
     Depositor<NB> dep{dscr + wid};
     // the spill area is sized in full records; compact records fit in it
     SRec* spill = reinterpret_cast<SRec*>(spill_all + (size_t)(blockIdx.x * WPB + wid) * spill_cap);
@@ -578,23 +581,23 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
         const uint64_t sp = __ballot(ev == kSplit);
         if (sp) {
             const int need = __popcll(sp);
-            if (top + need > kStackCap) {
+            if (top + need > stack_cap) {
                 // move the oldest entries to the top of the spill area
-                const int m = top + need - kStackCap;
+                const int m = top + need - stack_cap;
                 for (int i = lane; i < m; i += 64) {
                     const uint32_t g = nspill + (uint32_t)i;
                     if (g < spill_cap)
-                        spill[g] = stk[(base + i) & (kStackCap - 1)];
+                        spill[g] = stk[(base + i) & cmask];
                     else
                         atomicAdd(&A.counters[kQueueOverflow], 1ull);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 spilled += (uint32_t)m;
                 nspill = min(spill_cap, nspill + (uint32_t)m);
-                base = (base + m) & (kStackCap - 1);
+                base = (base + m) & cmask;
                 top -= m;
             }
-            if (ev == kSplit) stk[(base + top + __popcll(sp & lt)) & (kStackCap - 1)] = family_rec<NB>(ray);
+            if (ev == kSplit) stk[(base + top + __popcll(sp & lt)) & cmask] = family_rec<NB>(ray);
             top += need;
         }
         if (ev != kContinue) has = false;
@@ -609,7 +612,7 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
             const int rank = __popcll(idle & lt);
             const int nfam = min(nidle >> 2, top);
             if (!has && rank < 4 * nfam) {
-                r = family_child<NB>(stk[(base + top - 1 - (rank >> 2)) & (kStackCap - 1)], rank & 3);
+                r = family_child<NB>(stk[(base + top - 1 - (rank >> 2)) & cmask], rank & 3);
                 got = true;
             }
             top -= nfam;
@@ -669,27 +672,32 @@ constexpr int kMaxWavesPerBlock = 8;
 
 int persistent_max_waves() { return kMaxWavesPerBlock; }
 
-// LDS of a persistent workgroup of WPB waves (ray stacks and deposit scratch).
-template <int NB, int WPB>
-constexpr size_t persistent_lds_bytes() { return (size_t)WPB * (kStackCap * sizeof(StackRec<NB>) + sizeof(DepScratch<NB>)); }
+// LDS of a persistent workgroup of `waves` waves: the stacks (dynamic) and the deposit scratch.
+template <int NB>
+size_t persistent_stack_bytes(int waves, int stack_cap) { return (size_t)waves * stack_cap * sizeof(StackRec<NB>); }
+template <int NB>
+size_t persistent_lds_bytes(int waves, int stack_cap)
+{
+    return persistent_stack_bytes<NB>(waves, stack_cap) + (size_t)waves * sizeof(DepScratch<NB>);
+}
 constexpr size_t kLdsPerCu = 163840;
 
 template <int NB, int PREC, bool CORR, bool THIN>
 static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const uint32_t* n_items, uint32_t* head,
                                 RayRec* spill, uint32_t spill_cap, int blocks, int waves, int refill, int fam,
-                                hipStream_t s)
+                                int stack_cap, hipStream_t s)
 {
+    // eight waves only where their LDS fits a compute unit (else four, in twice the blocks)
+    if (waves == 8 && persistent_lds_bytes<NB>(8, stack_cap) > kLdsPerCu) {
+        waves = 4;
+        blocks *= 2;
+    }
+    const size_t dyn = persistent_stack_bytes<NB>(waves, stack_cap);
     switch (waves) {
-        case 1: k_trace_persistent<NB, PREC, 1, CORR, THIN><<<blocks, 64, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam); break;
-        case 2: k_trace_persistent<NB, PREC, 2, CORR, THIN><<<blocks, 128, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam); break;
-        case 4: k_trace_persistent<NB, PREC, 4, CORR, THIN><<<blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam); break;
-        default:
-            // eight waves only where their LDS fits a compute unit (else four, in twice the blocks)
-            if constexpr (persistent_lds_bytes<NB, 8>() <= kLdsPerCu)
-                k_trace_persistent<NB, PREC, 8, CORR, THIN><<<blocks, 512, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam);
-            else
-                k_trace_persistent<NB, PREC, 4, CORR, THIN><<<2 * blocks, 256, 0, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam);
-            break;
+        case 1: k_trace_persistent<NB, PREC, 1, CORR, THIN><<<blocks, 64, dyn, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam, stack_cap); break;
+        case 2: k_trace_persistent<NB, PREC, 2, CORR, THIN><<<blocks, 128, dyn, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam, stack_cap); break;
+        case 4: k_trace_persistent<NB, PREC, 4, CORR, THIN><<<blocks, 256, dyn, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam, stack_cap); break;
+        default: k_trace_persistent<NB, PREC, 8, CORR, THIN><<<blocks, 512, dyn, s>>>(A, items, n_items, head, spill, spill_cap, refill, fam, stack_cap); break;
     }
     return hipGetLastError();
 }
@@ -697,25 +705,26 @@ static hipError_t persistent_nb(const TraceArgs& A, const RayRec* items, const u
 template <int NB>
 static hipError_t persistent_variant(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
                                      uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
-                                     int refill, int fam, hipStream_t s)
+                                     int refill, int fam, int stack_cap, hipStream_t s)
 {
     const bool thin = A.r_out != nullptr;
-    if (prec != 0) return persistent_nb<NB, 1, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
-    if (A.corr && thin) return persistent_nb<NB, 0, true, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
-    if (A.corr) return persistent_nb<NB, 0, true, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
-    if (thin) return persistent_nb<NB, 0, false, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
-    return persistent_nb<NB, 0, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+    if (prec != 0) return persistent_nb<NB, 1, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
+    if (A.corr && thin) return persistent_nb<NB, 0, true, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
+    if (A.corr) return persistent_nb<NB, 0, true, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
+    if (thin) return persistent_nb<NB, 0, false, true>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
+    return persistent_nb<NB, 0, false, false>(A, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
 }
 
 hipError_t launch_trace_persistent(const TraceArgs& A, int prec, const RayRec* items, const uint32_t* n_items,
                                    uint32_t* head, RayRec* spill, uint32_t spill_cap, int blocks, int waves,
-                                   int refill, int fam, hipStream_t s)
+                                   int refill, int fam, int stack_cap, hipStream_t s)
 {
+    if (stack_cap != 64 && stack_cap != 128 && stack_cap != 256) return hipErrorInvalidValue;
     switch (A.nb) {
-        case 1: return persistent_variant<1>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
-        case 2: return persistent_variant<2>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
-        case 3: return persistent_variant<3>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
-        default: return persistent_variant<4>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, s);
+        case 1: return persistent_variant<1>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
+        case 2: return persistent_variant<2>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
+        case 3: return persistent_variant<3>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
+        default: return persistent_variant<4>(A, prec, items, n_items, head, spill, spill_cap, blocks, waves, refill, fam, stack_cap, s);
     }
 }
 

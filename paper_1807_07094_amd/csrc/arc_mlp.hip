@@ -351,7 +351,22 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
 {
     const Model* M = a.model;
     __shared__ LdsWeights w;
+    // the gate's verdict per bin (enough samples, small held-out error) as one bit each, so that
+    // a cell's gate test reads LDS instead of two scattered loads from the model's tables
+    __shared__ uint32_t gate_ok[kGateBins / 32];
     load_lds_weights(M, w);
+    if (a.gated) {
+        static_assert(kGateBins % 256 == 0, "whole rounds of the workgroup over the bins");
+        for (uint32_t bin = threadIdx.x; bin < (uint32_t)kGateBins; bin += blockDim.x) {
+            const bool ok = M->gate_count[bin] >= a.gate_min_count && M->gate_err[bin] <= a.gate_tol;
+            const uint64_t bits = __ballot(ok);
+            // lane 0 of each wave holds the 64 bins (two words) starting at its own bin
+            if ((threadIdx.x & 63) == 0) {
+                gate_ok[bin >> 5] = (uint32_t)bits;
+                gate_ok[(bin >> 5) + 1] = (uint32_t)(bits >> 32);
+            }
+        }
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const Scales z = scales_of(M);
@@ -385,7 +400,7 @@ __global__ __launch_bounds__(256) void k_infer(InferArgs a)
                 const int b = min(kGate - 1, max(0, (int)(u * kGate)));
                 bin = bin * kGate + (uint32_t)b;
             }
-            accept = accept && M->gate_count[bin] >= a.gate_min_count && M->gate_err[bin] <= a.gate_tol;
+            accept = accept && ((gate_ok[bin >> 5] >> (bin & 31u)) & 1u) != 0u;
         }
         float xn = 0.0f, Tn = 0.0f;
         chem::Coef k{};

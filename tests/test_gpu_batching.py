@@ -69,6 +69,7 @@ def test_autotuner_shape_matches_plain_bitwise(arc, ctx):
     assert res["candidates"] >= 10
     assert res["waves"] in (2, 4, 8) and res["waves_per_cu"] in (8, 12, 16)
     assert res["refill"] in (16, 32, 48, 56, 64) and 5 <= res["item_delta"] <= 7
+    assert res["stack"] in (64, 128, 256)
     assert 0 < res["ms_best"] <= res["ms_default"]
     tuned = run_gpu_trace(arc, ctx, w, schedule="batched_tuned")
     assert np.array_equal(tuned["J"], plain["J"])
@@ -145,6 +146,9 @@ def test_spill_area_overflow_is_reported_and_context_reused(arc, ctx):
     assert np.array_equal(again["J"], p["J"])
     with pytest.raises(arc.ArcError) as e:
         run_gpu_trace(arc, ctx, w, schedule="batched", spill_cap=-1)
+    assert e.value.status == -1
+    with pytest.raises(arc.ArcError) as e:
+        run_gpu_trace(arc, ctx, w, schedule="batched", tune_stack=96)
     assert e.value.status == -1
 
 

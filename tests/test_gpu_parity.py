@@ -97,11 +97,16 @@ def test_plain_equals_batched_bitwise_and_repeatable(arc, ctx):
     # refills that leave lanes no whole family fits, and refills only of a fully idle wave
     e = run_gpu_trace(arc, ctx, w, schedule="batched", tune_waves=1, tune_refill=3, tune_blocks=11)
     f = run_gpu_trace(arc, ctx, w, schedule="batched", tune_waves=8, tune_refill=64, tune_blocks=5)
+    # deeper LDS stacks (the autotuner's stack depth), eight waves at the largest
+    g = run_gpu_trace(arc, ctx, w, schedule="batched", tune_waves=8, tune_stack=256, tune_blocks=9)
+    h = run_gpu_trace(arc, ctx, w, schedule="batched", tune_waves=2, tune_stack=128, tune_refill=16)
     assert np.array_equal(a["J"], b["J"])
     assert np.array_equal(b["J"], c["J"])
     assert np.array_equal(b["J"], d["J"])
     assert np.array_equal(b["J"], e["J"])
     assert np.array_equal(b["J"], f["J"])
+    assert np.array_equal(b["J"], g["J"])
+    assert np.array_equal(b["J"], h["J"])
     assert e["ledger"]["crossings"] == f["ledger"]["crossings"] == a["ledger"]["crossings"]
     assert np.array_equal(a["gamma"], b["gamma"])
     assert a["ledger"]["crossings"] == b["ledger"]["crossings"] == c["ledger"]["crossings"]
