@@ -28,12 +28,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Valid for the kernel sources with these digests; with any other sources they are stale and
 # reported as null.
 MEASURED_COUNTERS = {
-    "bytes_per_crossing": 15.72,
-    "valu_per_crossing": 5.832,
-    "l2_hit_rate": 0.0943,
+    "bytes_per_crossing": 14.93,
+    "valu_per_crossing": 5.836,
+    "l2_hit_rate": 0.0995,
     "sha256": {
-        "paper_1807_07094_amd/csrc/arc_device.h": "bdb15bc8cf3471f763d07b2d97f875bb5f0df04c4efdf0ebe8721b2ef88d84c1",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "10f61fb91323858a15e30b91ccd87112655f84c0b5903afc59f8a0ac2fddc894",
+        "paper_1807_07094_amd/csrc/arc_device.h": "8db5fd1e715339ecbe8fd67d4b6ed5cde867533205a4d23a55bb8669953d5e50",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "403ec961c88305a494fc9f8458e16d5238f5f65219914e3a1087dff6d4a9bc64",
     },
     "profile": "profiles/hbm_l2_sq_k_trace_persistent_grf1024_16384src.md",
 }
