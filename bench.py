@@ -33,7 +33,7 @@ MEASURED_COUNTERS = {
     "l2_hit_rate": 0.0995,
     "sha256": {
         "paper_1807_07094_amd/csrc/arc_device.h": "8db5fd1e715339ecbe8fd67d4b6ed5cde867533205a4d23a55bb8669953d5e50",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "403ec961c88305a494fc9f8458e16d5238f5f65219914e3a1087dff6d4a9bc64",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "b6d671a4afc4e60951f300c84167e839e8ddccade6598383078285b75af53bba",
     },
     "profile": "profiles/hbm_l2_sq_k_trace_persistent_grf1024_16384src.md",
 }

@@ -526,12 +526,13 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 // iteration. A splitting lane pushes one family record (the ray, from which its four children
 // are derived) and goes idle with the lanes whose ray ended; once at least `refill` lanes are
 // idle they are refilled with whole families from the wave's LDS stack, then from the wave's
-// private spill area, and when both are empty from the global work queue of subtree roots (one
-// atomic per refill); every new ray of the iteration is started in one place. The stack's top
-// holds the latest splits, so the four children of a ray, and the children of rays that split
-// together, enter together and cross the same cells in the same passes: the wave's deposit
-// merge then sums their crossings of a cell into one atomic item (the kernel's throughput is
-// that of the int64 atomics in L2). The LDS stack is a ring: when it would overflow, its
+// private spill area, and when both are empty from the global work queue (one atomic per
+// refill; its items are the family records the last level-synchronous launch left, or single
+// root rays when there was none); every new ray of the iteration is started in one place. The
+// stack's top holds the latest splits, so the four children of a ray, and the children of rays
+// that split together, enter together and cross the same cells in the same passes: the wave's
+// deposit merge then sums their crossings of a cell into one atomic item (the int64 atomics in
+// L2 and the VALU issue share the limit of this kernel). The LDS stack is a ring: when it would overflow, its
 // oldest entries move to the top of the spill area, so the pair behaves as one LIFO stack and
 // the wave works depth first. Waves share nothing but the work-queue head, so each wave ends
 // when the queue is drained and its own stacks are empty.
