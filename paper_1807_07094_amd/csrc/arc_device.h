@@ -674,11 +674,15 @@ __device__ __forceinline__ int deposit_seg_corr(const TraceArgs& A, Ray<NB>& ray
 // window of four (256 crossings) fits the LDS of three waves per SIMD beside the family
 // stacks, and the kernel's time follows the atomic items it leaves (1024^3 x 16384 sources:
 // windows of two and ten segments ahead, 0.273 items per crossing and 715 ms; windows of four
-// and eight ahead, 0.236 and 686 ms).
+// and eight ahead, 0.236 and 686 ms; twelve ahead, 682 ms). With thin spheres the extra state
+// leaves room for eight only (twelve spill registers).
 #ifndef ARC_SEG_AHEAD
-#define ARC_SEG_AHEAD 8
+#define ARC_SEG_AHEAD 12
 #endif
 constexpr int kSegAhead = ARC_SEG_AHEAD;
+constexpr int kSegAheadThin = 8;
+template <bool THIN>
+constexpr int seg_ahead() { return THIN ? kSegAheadThin : kSegAhead; }
 #ifndef ARC_DEP_WINDOW
 #define ARC_DEP_WINDOW 4
 #endif

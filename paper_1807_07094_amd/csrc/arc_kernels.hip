@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_trace_rays(TraceArgs A, const RayRec* _
             if constexpr (CORR)
                 e = trace_pass_corr<NB, PREC, kSegAheadCorr, THIN>(A, ray, act, st, dep);
             else
-                e = trace_pass<NB, PREC, kSegAhead, THIN>(A, ray, act, st, dep);
+                e = trace_pass<NB, PREC, seg_ahead<THIN>(), THIN>(A, ray, act, st, dep);
             if (act && e != kContinue) {
                 ev = e;
                 act = false;
@@ -522,8 +522,8 @@ hipError_t launch_trace_rays(const TraceArgs& A, int prec, const RayRec* in, con
 // Batched schedule: after the first levels have been traced level by level (so that there
 // are enough independent subtrees), one persistent launch traces every remaining subtree.
 //
-// Each wave keeps 64 rays in flight, one per lane, and advances them up to kSegAhead crossings per
-// iteration. A splitting lane pushes one family record (the ray, from which its four children
+// Each wave keeps 64 rays in flight, one per lane, and advances them up to seg_ahead crossings
+// per iteration. A splitting lane pushes one family record (the ray, from which its four children
 // are derived) and goes idle with the lanes whose ray ended; once at least `refill` lanes are
 // idle they are refilled with whole families from the wave's LDS stack, then from the wave's
 // private spill area, and when both are empty from the global work queue (one atomic per
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(WPB * 64, NB <= 3 ? 3 : 2) void k_trace_persistent(
             if constexpr (CORR)
                 ev = trace_pass_corr<NB, PREC, kSegAheadCorr, THIN>(A, ray, has, st, dep);
             else
-                ev = trace_pass<NB, PREC, kSegAhead, THIN>(A, ray, has, st, dep);
+                ev = trace_pass<NB, PREC, seg_ahead<THIN>(), THIN>(A, ray, has, st, dep);
         }
         // splits: one family record each
         const uint64_t sp = __ballot(ev == kSplit);
