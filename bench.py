@@ -28,12 +28,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Valid for the kernel sources with these digests; with any other sources they are stale and
 # reported as null.
 MEASURED_COUNTERS = {
-    "bytes_per_crossing": 14.93,
-    "valu_per_crossing": 5.836,
-    "l2_hit_rate": 0.0995,
+    "bytes_per_crossing": 15.47,
+    "valu_per_crossing": 5.924,
+    "l2_hit_rate": 0.0803,
     "sha256": {
-        "paper_1807_07094_amd/csrc/arc_device.h": "8db5fd1e715339ecbe8fd67d4b6ed5cde867533205a4d23a55bb8669953d5e50",
-        "paper_1807_07094_amd/csrc/arc_kernels.hip": "b6d671a4afc4e60951f300c84167e839e8ddccade6598383078285b75af53bba",
+        "paper_1807_07094_amd/csrc/arc_device.h": "e391af014143268c460e533da8fb189835cb8300db2c07f183a9defa19897767",
+        "paper_1807_07094_amd/csrc/arc_kernels.hip": "25d63b65c69587935ee0fbd9f93d932980bec682d193fdaac6f984ae9fbc878e",
     },
     "profile": "profiles/hbm_l2_sq_k_trace_persistent_grf1024_16384src.md",
 }
