@@ -163,3 +163,29 @@ def test_every_work_item_level_equals_plain_bitwise(arc, ctx, delta):
     assert np.array_equal(b["J"], p["J"])
     assert b["ledger"]["rays"] == p["ledger"]["rays"]
     assert b["ledger"]["crossings"] == p["ledger"]["crossings"]
+
+
+@pytest.mark.parametrize("delta", [1, 3])
+def test_family_work_items_with_the_correction_equal_plain_bitwise(arc, ctx, delta):
+    """The family records between the two stages, in the geometric correction's kernels: the
+    field and both limbs of the moved-photon field as the plain schedule's."""
+    w = W.lognormal(40, 12, 23)
+    p = run_gpu_trace(arc, ctx, w, schedule="plain", correction="conserving")
+    b = run_gpu_trace(arc, ctx, w, schedule="batched", correction="conserving",
+                      tune_item_level=w.trace["level0"] + delta)
+    for k in ("J", "moved_lo", "moved_hi"):
+        assert np.array_equal(b[k], p[k]), k
+    assert b["ledger"]["rays"] == p["ledger"]["rays"]
+
+
+@pytest.mark.parametrize("delta", [1, 3])
+def test_family_work_items_with_thin_spheres_equal_plain_bitwise(arc, ctx, delta):
+    """The family records between the two stages, in the thin-sphere kernels: rays of sources
+    whose thin radius lies beyond a level's split radius split at once."""
+    w = W.lognormal(40, 6, 24, source_cells="uniform")
+    w.sources["r_thin"] = np.array([0.0, 0.4, 1.5, 3.0, 6.0, 12.0])
+    p = run_gpu_trace(arc, ctx, w, schedule="plain")
+    b = run_gpu_trace(arc, ctx, w, schedule="batched", tune_item_level=w.trace["level0"] + delta)
+    assert np.array_equal(b["J"], p["J"])
+    assert b["ledger"]["rays"] == p["ledger"]["rays"]
+    assert b["ledger"]["crossings"] == p["ledger"]["crossings"]
